@@ -1,0 +1,228 @@
+/*
+ * libov -- overlap fermion operator D_ov = 1 + gamma5 sign(H_w) on one AMD
+ * MI355X (gfx950).  Plain C ABI: opaque context, plain pointers and sizes.
+ *
+ * Paper: "Electric polarizability of hadrons with overlap fermions on
+ * multi-GPUs" (Lattice 2011).  Every entry point names the passage that
+ * defines the operation it performs.
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ * Lattice L = (Lx, Ly, Lz, Lt), V = Lx*Ly*Lz*Lt sites, canonical site index
+ * i = x + Lx*(y + Ly*(z + Lz*t)).  Directions mu = 0,1,2,3 are x,y,z,t.
+ *
+ * Canonical device layouts (complex128 = interleaved re,im doubles):
+ *   spinor batch  [nrhs][V][4 spin][3 colour]
+ *   gauge field   [4 mu][V][3][3]     (row a, column b; U_mu(i) links i -> i+mu)
+ *   small space   [l][V][4][3]        (orthonormal columns)
+ * Every pointer argument named *_dev is a device pointer that the caller owns
+ * and keeps alive for the duration of the call (stream-ordered on the stream
+ * set with ov_set_stream).  Host arrays are read before the call returns.
+ * The context owns every internal buffer (packed links, small spaces,
+ * deflation basis, workspaces); its memory is released by ov_destroy.
+ *
+ * Gamma matrices (chiral basis): gamma_k = [[0,-i sigma_k],[i sigma_k,0]],
+ * gamma_4 = [[0,1],[1,0]], gamma5 = gamma1 gamma2 gamma3 gamma4 = diag(1,1,-1,-1).
+ * Wilson operator:
+ *   D_w psi(x) = (4 + m_w) psi(x)
+ *     - 1/2 sum_mu [ (1 - gamma_mu) U~_mu(x) psi(x+mu) + (1 + gamma_mu) U~_mu(x-mu)^dag psi(x-mu) ]
+ * with U~_0(x) = exp(i q eta t) U_0(x) (background field, Sec. 4 eq. (3)) and
+ * the boundary multiplier b_mu (+1 periodic, -1 antiperiodic, 0 Dirichlet)
+ * on hops that wrap around the lattice (Sec. 4: Dirichlet in the field
+ * direction and in time).  H_w = gamma5 D_w (Sec. 2).
+ *
+ * Precision codes select the INTERNAL arithmetic and storage; I/O is always
+ * complex128.  OV_FP64: double.  OV_FP32: float links and spinors, float
+ * Clenshaw recursion, FP64 small-space projection.  OV_BF16: bfloat16 storage
+ * of links and spinors, float arithmetic, FP64 projection.
+ *
+ * Errors: every entry point returns OV_OK (0) or a negative status; no
+ * exception or abort crosses the ABI.  After an error the context stays
+ * usable, outputs are unspecified, and ov_last_error() describes the cause.
+ * One context per host thread.
+ */
+#ifndef OV_H
+#define OV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ov_ctx ov_ctx;
+
+enum {
+    OV_OK = 0,
+    OV_EINVAL = -1,   /* bad argument (shape, range, null pointer)           */
+    OV_ENOMEM = -2,   /* device allocation failed or over the memory budget   */
+    OV_EHIP = -3,     /* HIP runtime error                                    */
+    OV_ENOCONV = -4,  /* CG reached maxiter; best iterate and report written  */
+    OV_ENAN = -5,     /* NaN/Inf detected in an input or a residual           */
+    OV_ESTATE = -6,   /* call out of order (e.g. no gauge field uploaded)     */
+    OV_ENORM = -7     /* norm bound below ||H_w|| detected (Clenshaw growth)  */
+};
+
+enum { OV_FP64 = 0, OV_FP32 = 1, OV_BF16 = 2 };
+enum { OV_PERIODIC = 0, OV_ANTIPERIODIC = 1, OV_DIRICHLET = 2 };
+enum { OV_OP_DW = 0, OV_OP_HW = 1 };
+
+/*
+ * Create a context for lattice L with boundary codes bc (per direction) and
+ * Wilson mass m_w on HIP device `device`.  Sizes must be >= 2 (Lt >= 2) and
+ * V < 2^31.  On success *out owns the context.
+ */
+int ov_create(const int32_t L[4], const int32_t bc[4], double m_w, int device, ov_ctx **out);
+
+/* Free every device buffer and the context.  Accepts NULL. */
+int ov_destroy(ov_ctx *ctx);
+
+/* Run all further work on this hipStream_t (NULL = the null stream, the default). */
+int ov_set_stream(ov_ctx *ctx, void *hip_stream);
+
+/* Human-readable description of the last error on this context. */
+const char *ov_last_error(const ov_ctx *ctx);
+
+/*
+ * Upload the base SU(3)-valued links (canonical [4][V][3][3] complex128 on
+ * the device).  Packed into the context's internal layouts for every
+ * precision.  Sec. 2 (D_w) and Sec. 4 (links that the background field
+ * multiplies).  Returns OV_ENAN if the field holds NaN/Inf.
+ */
+int ov_upload_gauge(ov_ctx *ctx, const void *U_dev);
+
+/*
+ * Define nfield background-field groups: group f multiplies the mu = 0 links
+ * by exp(i q[f] eta[f] t) (Sec. 4, eq. (3); the operator depends on q*eta
+ * only).  Host arrays of length nfield (1 <= nfield <= 64).  Resets any small
+ * space and deflation basis uploaded before.
+ */
+int ov_set_fields(ov_ctx *ctx, int nfield, const double *q, const double *eta);
+
+/*
+ * Polynomial parameters of sign(H_w) ~ Q P(Q^2), Q = H_w / norm (Sec. 2):
+ * degree n >= 1 in Q^2, interval [eps, 1] for Q^2 (0 < eps < 1), and
+ * norm >= ||H_w|| (the default bound |4+m_w| + 4 is valid for any links;
+ * pass norm <= 0 to use it).  coeffs: host array of n+1 Chebyshev
+ * coefficients c_k of P(y) = sum c_k T_k((2y-1-eps)/(1-eps)), or NULL to use
+ * the Chebyshev interpolant of y^{-1/2} at the n+1 Chebyshev-Gauss nodes.
+ */
+int ov_set_sign_params(ov_ctx *ctx, int n, double eps, double norm, const double *coeffs);
+
+/*
+ * Small space of group `field` (Sec. 2, Fig. 1: lowest |lambda| eigenvectors
+ * of H_w, treated exactly): l orthonormal vectors V_dev [l][V][4][3]
+ * complex128 and their H_w eigenvalues lambda (host, length l; only the sign
+ * is used, sgn(0) := +1).  l = 0 clears it.  Orthonormality is checked in
+ * FP64: returns OV_EINVAL if max |V^dag V - 1| > 1e-8.
+ */
+int ov_upload_eigvecs(ov_ctx *ctx, int field, int l, const void *V_dev, const double *lambda);
+
+/*
+ * Deflation basis of group `field` for the CG (Sec. 2 end, Sec. 3.1: low
+ * modes of the overlap operator speed up CG): k orthonormal vectors W_dev
+ * [k][V][4][3].  The library computes a_i = ||D_ov w_i||^2 and
+ * b_i = Re<w_i, D_ov w_i> in FP64 so that the Galerkin diagonal for mass m
+ * is (1-m/2)^2 a_i + 2 m (1-m/2) b_i + m^2.  Needs the gauge field, the sign
+ * parameters and the small space first (OV_ESTATE otherwise).
+ */
+int ov_upload_deflation(ov_ctx *ctx, int field, int k, const void *W_dev);
+
+/*
+ * y = D_w x (op = OV_OP_DW) or y = H_w x = gamma5 D_w x (op = OV_OP_HW) for
+ * nrhs fields, RHS j using background group field_of_rhs[j] (host array).
+ * x_dev, y_dev: [nrhs][V][4][3] complex128, must not overlap.  Sec. 2 (H_w).
+ */
+int ov_dslash(ov_ctx *ctx, int prec, int op, int nrhs, const int *field_of_rhs,
+              const void *x_dev, void *y_dev);
+
+/*
+ * y = s(x) = V sgn(lambda) V^dag x + Pi Q P(Q^2) Pi x with Pi = 1 - V V^dag
+ * (Sec. 2: small space exact, polynomial on the rest), per RHS with the small
+ * space of its group.  Cost: 2n+1 H_w applications.  x_dev, y_dev as in
+ * ov_dslash; may alias.
+ */
+int ov_sign_apply(ov_ctx *ctx, int prec, int nrhs, const int *field_of_rhs,
+                  const void *x_dev, void *y_dev);
+
+/*
+ * y = D(m) x with D(m) = (1 - m/2) D_ov + m, D_ov = 1 + gamma5 s (Sec. 2,
+ * eq. (1); m = 0 is eq. (1) itself), or y = D(m)^dag x = gamma5 D(m) gamma5 x
+ * when dagger != 0.  mass: host array of nrhs quark masses.
+ */
+int ov_dov_apply(ov_ctx *ctx, int prec, int nrhs, const int *field_of_rhs, const double *mass,
+                 int dagger, const void *x_dev, void *y_dev);
+
+typedef struct {
+    double tol;        /* stop when ||D^dag b - A x|| / ||D^dag b|| <= tol (FP64 true residual) */
+    int maxiter;       /* cap on inner iterations summed over restarts                         */
+    int inner_prec;    /* OV_FP64, OV_FP32 or OV_BF16 arithmetic of the inner CG               */
+    double inner_tol;  /* relative residual reduction per inner solve (e.g. 1e-5 for FP32)     */
+    int max_restarts;  /* cap on FP64 defect-correction restarts                               */
+    int use_deflation; /* apply the uploaded deflation basis at each restart                   */
+} ov_cg_opts;
+
+typedef struct {
+    int iters;         /* inner CG iterations (each = 2 D_ov applies per active RHS)           */
+    int restarts;      /* FP64 residual evaluations                                            */
+    double relres;     /* final FP64 true relative residual                                    */
+    int status;        /* OV_OK or OV_ENOCONV                                                  */
+} ov_cg_rhs_report;
+
+/*
+ * Solve D(m)^dag D(m) x = D(m)^dag b, i.e. x = D(m)^{-1} b, for nrhs right-hand
+ * sides (Sec. 3.2: CG for overlap propagators; single precision late in the
+ * solve; deflation by overlap low modes).  Outer loop in FP64 (true residual,
+ * deflation step x += W Lambda^{-1} W^dag r), inner CG in opts->inner_prec,
+ * x += e in FP64.  x_dev holds the initial guess on entry (zero is fine) and
+ * the solution on return.  report: host array of nrhs entries (may be NULL).
+ * Returns OV_ENOCONV if any RHS did not converge (its best iterate is kept).
+ * Synchronises the stream.
+ */
+int ov_deflated_cg(ov_ctx *ctx, int nrhs, const int *field_of_rhs, const double *mass,
+                   const void *b_dev, void *x_dev, const ov_cg_opts *opts,
+                   ov_cg_rhs_report *report);
+
+/*
+ * Adjoint of the sign function for L = Re<g, s(U, eta) x> with the small
+ * space, the polynomial and the norm held fixed (background field, Sec. 4,
+ * eq. (3)).  One RHS of group `field`.  Outputs (any may be NULL):
+ *   gU_dev   [4][V][3][3] complex128, dL/dRe U + i dL/dIm U of the BASE links;
+ *   geta     host double, dL/d eta of this group (charge q held fixed);
+ *   gx_dev   [V][4][3] complex128, dL/dRe x + i dL/dIm x = s g.
+ * The forward Clenshaw vectors are checkpointed every ckpt_every terms
+ * (>= 1) and replayed segment by segment.  FP64 throughout.  Synchronises.
+ */
+int ov_sign_backward(ov_ctx *ctx, int field, const void *x_dev, const void *g_dev,
+                     void *gU_dev, double *geta, void *gx_dev, int ckpt_every);
+
+/*
+ * Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch of the named kernel class ("dslash", "clenshaw", "proj_dot",
+ * "proj_expand", "blas", "force").  ov_prof_enable(ctx, 1) starts a fresh
+ * window; ov_prof_query synchronises and returns the launch count, the summed
+ * duration in ms and the summed algorithmic HBM bytes of those launches.
+ */
+int ov_prof_enable(ov_ctx *ctx, int on);
+int ov_prof_query(ov_ctx *ctx, const char *kernel_class, long *launches, double *total_ms,
+                  double *bytes);
+
+/*
+ * Kernel launch tuning of the dslash family: RHS per thread (1, 2, 4, 8) and
+ * threads per workgroup (64..1024, multiple of 64) for precision prec.
+ * ov_autotune times the candidates on the current context for nrhs RHS,
+ * keeps the fastest and, with a non-NULL cache_path, records it there as a
+ * one-line JSON object per key.
+ */
+int ov_set_tuning(ov_ctx *ctx, int prec, int rhs_per_thread, int block);
+int ov_get_tuning(ov_ctx *ctx, int prec, int *rhs_per_thread, int *block);
+int ov_autotune(ov_ctx *ctx, int prec, int nrhs, const char *cache_path);
+
+/* Bytes of device memory the context holds right now. */
+int ov_memory_used(const ov_ctx *ctx, int64_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OV_H */

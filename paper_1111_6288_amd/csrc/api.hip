@@ -1,0 +1,1660 @@
+// libov host side: the context, its device memory, the drivers of the
+// overlap pipeline and every extern "C" entry point of include/ov.h.
+//
+// Pipeline of one sign application on a batch (Sec. 2):
+//   C = V^dag x, chi = x - V C                       (FP64 projection, matrix cores)
+//   Clenshaw b_k = c_k chi + 2 T b_{k+1} - b_{k+2}, k = n..1,
+//     T = (2 Q^2 - (1+eps)) / (1-eps), Q = H_w / norm:  two dslash launches per
+//     step, the second one with the recursion fused into its epilogue
+//   z = c_0 chi + T b_1 - b_2, w = Q z
+//   s = w - V (V^dag w) + V sgn(lambda) C            (FP64 projection)
+// D(m) = (1 - m/2)(1 + gamma5 s) + m (eq. (1) with a quark mass), and the CG
+// of Sec. 3.2 runs on D(m)^dag D(m) with FP64 defect correction around an
+// inner solve in the requested precision.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "ov.h"
+#include "ov_internal.h"
+
+using namespace ov;
+
+namespace {
+
+enum ProfClass { PC_DSLASH = 0, PC_CLENSHAW, PC_PROJ_DOT, PC_PROJ_EXPAND, PC_BLAS, PC_FORCE, PC_N };
+const char *kProfNames[PC_N] = {"dslash", "clenshaw", "proj_dot", "proj_expand", "blas", "force"};
+
+struct ProfRec {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+};
+
+struct Small {
+    int l = 0;
+    double2 *V = nullptr;     // planes [l][12][Vp]
+    double *sgn = nullptr;    // [l]
+};
+
+struct Defl {
+    int k = 0;
+    double2 *W = nullptr;     // planes [k][12][Vp]
+    std::vector<double> a, b; // ||D_ov w||^2, Re<w, D_ov w>
+};
+
+}  // namespace
+
+struct ov_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;   // caller's stream; nullptr is the null stream
+    int L[4] = {0, 0, 0, 0}, bc[4] = {0, 0, 0, 0};
+    double mw = 0;
+    Geo g{};
+    std::string err;
+
+    bool have_gauge = false;
+    double2 *U64 = nullptr;
+    float2 *U32 = nullptr;
+    uint32_t *U16 = nullptr;
+
+    int nfield = 0;
+    std::vector<double> q, eta;
+    cx<double> *phase = nullptr;     // [nfield][Lt]
+
+    bool have_sign = false;
+    int npoly = 0;
+    double eps = 0, norm = 0;
+    std::vector<double> coef;
+
+    std::vector<Small> small;
+    std::vector<Defl> defl;
+
+    // workspace arena (grow-only, sized at the start of each entry point)
+    char *ws = nullptr;
+    size_t ws_size = 0;
+    size_t ws_top = 0;
+
+    // content-keyed caches of small device arrays
+    std::map<std::vector<int>, int *> icache;
+    std::map<std::vector<double>, double *> dcache;
+    std::map<std::vector<double>, double2 *> ccache;
+
+    // tuning: rhs per thread and block per precision
+    int nr[3] = {2, 4, 4};
+    int block[3] = {128, 128, 128};
+
+    // profiling
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<ProfRec> recs;
+
+    // persistent small device scratch
+    int *d_count = nullptr;
+
+    size_t mem_bytes = 0;
+};
+
+namespace {
+
+int fail(ov_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(c, OV_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                          __FILE__, __LINE__);                                     \
+    } while (0)
+
+#define CHK(expr)                    \
+    do {                             \
+        int r_ = (expr);             \
+        if (r_ != OV_OK) return r_;  \
+    } while (0)
+
+int dev_alloc(ov_ctx *c, void **p, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(c, OV_ENOMEM, "hipMalloc of %.3f GB failed: %s", bytes / 1e9, hipGetErrorString(e));
+    }
+    c->mem_bytes += bytes;
+    return OV_OK;
+}
+
+void dev_free(ov_ctx *c, void *p, size_t bytes)
+{
+    if (p) {
+        (void)hipFree(p);
+        c->mem_bytes -= std::min(c->mem_bytes, bytes);
+    }
+}
+
+size_t field_elems(const ov_ctx *c) { return 12ul * c->g.Vp; }
+
+template <class S>
+size_t field_bytes(const ov_ctx *c) { return field_elems(c) * sizeof(S); }
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Make sure the arena holds `bytes`; only called before any pointer is handed out.
+int ws_reserve(ov_ctx *c, size_t bytes)
+{
+    c->ws_top = 0;
+    if (bytes <= c->ws_size) return OV_OK;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    dev_free(c, c->ws, c->ws_size);
+    c->ws = nullptr;
+    c->ws_size = 0;
+    CHK(dev_alloc(c, (void **)&c->ws, bytes));
+    c->ws_size = bytes;
+    // fresh workspace starts zeroed so that padding sites hold zeros
+    HIPCHK(hipMemsetAsync(c->ws, 0, bytes, c->stream));
+    return OV_OK;
+}
+
+template <class T>
+T *ws_take(ov_ctx *c, size_t count)
+{
+    size_t bytes = align_up(count * sizeof(T));
+    if (c->ws_top + bytes > c->ws_size) return nullptr;
+    T *p = (T *)(c->ws + c->ws_top);
+    c->ws_top += bytes;
+    return p;
+}
+
+// Host-to-device copy ordered on the context stream; returns once it landed.
+hipError_t h2d(ov_ctx *c, void *dst, const void *src, size_t bytes)
+{
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(c->stream);
+}
+
+const int *dev_ints(ov_ctx *c, const std::vector<int> &v)
+{
+    if (v.empty()) return nullptr;
+    auto it = c->icache.find(v);
+    if (it != c->icache.end()) return it->second;
+    int *p = nullptr;
+    if (dev_alloc(c, (void **)&p, v.size() * sizeof(int)) != OV_OK) return nullptr;
+    if (h2d(c, p, v.data(), v.size() * sizeof(int)) != hipSuccess) return nullptr;
+    c->icache[v] = p;
+    return p;
+}
+
+const double *dev_doubles(ov_ctx *c, const std::vector<double> &v)
+{
+    if (v.empty()) return nullptr;
+    auto it = c->dcache.find(v);
+    if (it != c->dcache.end()) return it->second;
+    double *p = nullptr;
+    if (dev_alloc(c, (void **)&p, v.size() * sizeof(double)) != OV_OK) return nullptr;
+    if (h2d(c, p, v.data(), v.size() * sizeof(double)) != hipSuccess) return nullptr;
+    c->dcache[v] = p;
+    return p;
+}
+
+// complex coefficients given as interleaved (re, im) pairs
+const double2 *dev_cplx(ov_ctx *c, const std::vector<double> &v)
+{
+    if (v.empty()) return nullptr;
+    auto it = c->ccache.find(v);
+    if (it != c->ccache.end()) return it->second;
+    double2 *p = nullptr;
+    if (dev_alloc(c, (void **)&p, v.size() * sizeof(double)) != OV_OK) return nullptr;
+    if (h2d(c, p, v.data(), v.size() * sizeof(double)) != hipSuccess) return nullptr;
+    c->ccache[v] = p;
+    return p;
+}
+
+// ---------------------------------------------------------------- profiling
+int prof_begin(ov_ctx *c)
+{
+    if (!c->prof_on) return -1;
+    if (c->ev_used + 2 > c->ev_pool.size()) {
+        for (int i = 0; i < 256; ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            c->ev_pool.push_back(e);
+        }
+    }
+    hipEvent_t a = c->ev_pool[c->ev_used++];
+    hipEvent_t b = c->ev_pool[c->ev_used++];
+    if (hipEventRecord(a, c->stream) != hipSuccess) return -1;
+    c->recs.push_back({-1, a, b, 0});
+    return (int)c->recs.size() - 1;
+}
+
+void prof_end(ov_ctx *c, int idx, int cls, double bytes)
+{
+    if (idx < 0) return;
+    c->recs[idx].cls = cls;
+    c->recs[idx].bytes = bytes;
+    (void)hipEventRecord(c->recs[idx].b, c->stream);
+}
+
+// ---------------------------------------------------------------- batches
+// A batch names fields by storage index; groups split it by background field.
+struct Batch {
+    int n = 0;
+    std::vector<int> slots_h;         // storage indices
+    const int *slots = nullptr;       // device copy (NULL when identity 0..n-1)
+    struct Grp {
+        int f;
+        std::vector<int> slots_h;
+        const int *slots;
+    };
+    std::vector<Grp> groups;
+};
+
+int make_batch(ov_ctx *c, const std::vector<int> &slots, const std::vector<int> &grp_of_slot, Batch &b)
+{
+    b = Batch();
+    b.n = (int)slots.size();
+    b.slots_h = slots;
+    bool ident = true;
+    for (int j = 0; j < b.n; ++j) ident = ident && slots[j] == j;
+    if (!ident) {
+        b.slots = dev_ints(c, slots);
+        if (!b.slots) return fail(c, OV_ENOMEM, "slot list upload failed");
+    }
+    std::map<int, std::vector<int>> by;
+    for (int j = 0; j < b.n; ++j) by[grp_of_slot[slots[j]]].push_back(slots[j]);
+    for (auto &kv : by) {
+        Batch::Grp g;
+        g.f = kv.first;
+        g.slots_h = kv.second;
+        g.slots = dev_ints(c, kv.second);
+        if (!g.slots) return fail(c, OV_ENOMEM, "group list upload failed");
+        b.groups.push_back(g);
+    }
+    return OV_OK;
+}
+
+// ---------------------------------------------------------------- precision map
+template <class S>
+struct PrecOf;
+template <>
+struct PrecOf<double2> {
+    static constexpr int p = OV_FP64;
+};
+template <>
+struct PrecOf<float2> {
+    static constexpr int p = OV_FP32;
+};
+template <>
+struct PrecOf<uint32_t> {
+    static constexpr int p = OV_BF16;
+};
+
+template <class S>
+const S *links_of(const ov_ctx *c);
+template <>
+const double2 *links_of<double2>(const ov_ctx *c) { return c->U64; }
+template <>
+const float2 *links_of<float2>(const ov_ctx *c) { return c->U32; }
+template <>
+const uint32_t *links_of<uint32_t>(const ov_ctx *c) { return c->U16; }
+
+// ---------------------------------------------------------------- launch helpers
+template <class S>
+int dslash_launch(ov_ctx *c, const Batch &b, const int *fgroup, const S *x, S *y, double a, bool hw,
+                  const S *e1 = nullptr, double c1 = 0, const S *e2 = nullptr, double c2 = 0,
+                  const S *e3 = nullptr, double c3 = 0)
+{
+    if (b.n == 0) return OV_OK;
+    DsArgs<S> d{};
+    d.x = x;
+    d.y = y;
+    d.fstride = (long)field_elems(c);
+    d.U = links_of<S>(c);
+    d.slots = b.slots;
+    d.n = b.n;
+    d.fgroup = fgroup;
+    d.phase = c->phase;
+    d.g = c->g;
+    d.diag = 4.0 + c->mw;
+    d.a = a;
+    d.e1 = e1;
+    d.e2 = e2;
+    d.e3 = e3;
+    d.c1 = c1;
+    d.c2 = c2;
+    d.c3 = c3;
+    const int P = PrecOf<S>::p;
+    int nr = c->nr[P];
+    while (nr > 1 && nr / 2 >= b.n) nr /= 2;
+    const bool epi = e1 || e2 || e3;
+    int pi = prof_begin(c);
+    HIPCHK(launch_dslash<S>(d, hw || epi, epi, nr, c->block[P], c->stream));
+    const double sb = sizeof(S);
+    const int nex = (e1 ? 1 : 0) + (e2 ? 1 : 0) + (e3 ? 1 : 0);
+    prof_end(c, pi, epi ? PC_CLENSHAW : PC_DSLASH,
+             (double)c->g.V * (36.0 * sb + (double)b.n * 12.0 * sb * (2 + nex)));
+    return OV_OK;
+}
+
+template <class SI, class SO>
+int lincomb(ov_ctx *c, const Batch &b, SO *out, int nin, const SI *const *in, const double2 *const *coefs,
+            const double2 *cconst, int g5mask, double *red = nullptr, int *nblk = nullptr)
+{
+    if (b.n == 0) return OV_OK;
+    LcArgs<SI, SO> a{};
+    a.nin = nin;
+    for (int t = 0; t < nin; ++t) {
+        a.in[t] = in[t];
+        a.istride[t] = (long)field_elems(c);
+        a.coef[t] = coefs ? coefs[t] : nullptr;
+        a.cconst[t] = cconst ? cconst[t] : make_double2(1.0, 0.0);
+    }
+    a.coef_by_slot = 1;
+    a.g5mask = g5mask;
+    a.out = out;
+    a.ostride = (long)field_elems(c);
+    a.slots = b.slots;
+    a.n = b.n;
+    a.Vp = c->g.Vp;
+    a.red = red;
+    int pi = prof_begin(c);
+    HIPCHK((launch_lincomb<SI, SO>(a, c->stream, nblk)));
+    prof_end(c, pi, PC_BLAS, (double)b.n * field_elems(c) * (nin * sizeof(SI) + sizeof(SO)));
+    return OV_OK;
+}
+
+// y = x (copy / precision conversion) for the entries of b
+template <class SI, class SO>
+int copy_fields(ov_ctx *c, const Batch &b, const SI *x, SO *y, int g5 = 0)
+{
+    const SI *in[1] = {x};
+    return lincomb<SI, SO>(c, b, y, 1, in, nullptr, nullptr, g5);
+}
+
+template <class S>
+int proj_dot(ov_ctx *c, const double2 *V, int l, const S *X, const Batch::Grp &gr, double2 *C, double2 *part)
+{
+    const int n = (int)gr.slots_h.size();
+    for (int j0 = 0; j0 < n; j0 += 48) {
+        const int nn = std::min(48, n - j0);
+        int pi = prof_begin(c);
+        HIPCHK(launch_proj_dot<S>(V, l, (long)field_elems(c), X, (long)field_elems(c), gr.slots + j0, nn, c->g.Vp,
+                                  0, part, C + (long)j0 * l, c->stream));
+        prof_end(c, pi, PC_PROJ_DOT, (double)field_elems(c) * (l * 16.0 + nn * (double)sizeof(S)));
+    }
+    return OV_OK;
+}
+
+template <class SX, class SY>
+int proj_expand(ov_ctx *c, const double2 *V, int l, const SX *X, double alpha, SY *Y, const Batch::Grp &gr,
+                const double2 *E, double beta)
+{
+    const int n = (int)gr.slots_h.size();
+    for (int j0 = 0; j0 < n; j0 += 48) {
+        const int nn = std::min(48, n - j0);
+        int pi = prof_begin(c);
+        HIPCHK((launch_proj_expand<SX, SY>(V, l, (long)field_elems(c), X, (long)field_elems(c), alpha, Y,
+                                           (long)field_elems(c), gr.slots + j0, nn, c->g.Vp, E + (long)j0 * l, beta,
+                                           c->stream)));
+        prof_end(c, pi, PC_PROJ_EXPAND,
+                 (double)field_elems(c) * (l * 16.0 + nn * (double)(sizeof(SY) + (X ? sizeof(SX) : 0))));
+    }
+    return OV_OK;
+}
+
+// ---------------------------------------------------------------- sign pipeline
+template <class S>
+struct SignBufs {
+    S *chi = nullptr, *B[3] = {nullptr, nullptr, nullptr}, *T = nullptr;
+    double2 *C = nullptr, *D = nullptr, *E = nullptr, *part = nullptr;
+};
+
+size_t small_arrays_bytes(const ov_ctx *c, int nstore)
+{
+    int lmax = 1;
+    for (auto &s : c->small) lmax = std::max(lmax, s.l);
+    for (auto &d : c->defl) lmax = std::max(lmax, d.k);
+    const long K = 12L * c->g.Vp;
+    const long nchunk = (K + proj_dot_chunk(K) - 1) / proj_dot_chunk(K);
+    return 3 * align_up((size_t)nstore * lmax * 16) + align_up((size_t)nchunk * 48 * 256 * 16);
+}
+
+template <class S>
+int take_sign_bufs(ov_ctx *c, int nstore, SignBufs<S> &w)
+{
+    const size_t fe = field_elems(c) * nstore;
+    w.chi = ws_take<S>(c, fe);
+    for (int i = 0; i < 3; ++i) w.B[i] = ws_take<S>(c, fe);
+    w.T = ws_take<S>(c, fe);
+    int lmax = 1;
+    for (auto &s : c->small) lmax = std::max(lmax, s.l);
+    for (auto &d : c->defl) lmax = std::max(lmax, d.k);
+    w.C = ws_take<double2>(c, (size_t)nstore * lmax);
+    w.D = ws_take<double2>(c, (size_t)nstore * lmax);
+    w.E = ws_take<double2>(c, (size_t)nstore * lmax);
+    const long K = 12L * c->g.Vp;
+    const long nchunk = (K + proj_dot_chunk(K) - 1) / proj_dot_chunk(K);
+    w.part = ws_take<double2>(c, (size_t)nchunk * 48 * 256);
+    if (!w.chi || !w.B[2] || !w.T || !w.part) return fail(c, OV_ENOMEM, "workspace too small (internal)");
+    return OV_OK;
+}
+
+template <class S>
+size_t sign_bufs_bytes(const ov_ctx *c, int nstore)
+{
+    return 5 * align_up(field_bytes<S>(c) * nstore) + small_arrays_bytes(c, nstore);
+}
+
+// OUT = s(X) on the batch.  OUT may alias X.  C/D/E hold per-group blocks at
+// offset (position of the group's first entry) * l.
+template <class S>
+int sign_batch(ov_ctx *c, const Batch &b, const int *fgroup, const S *X, S *OUT, SignBufs<S> &w)
+{
+    if (b.n == 0) return OV_OK;
+    if (!c->have_gauge) return fail(c, OV_ESTATE, "no gauge field uploaded");
+    if (!c->have_sign) return fail(c, OV_ESTATE, "sign parameters not set");
+    bool any_small = false;
+    for (auto &gr : b.groups) any_small = any_small || c->small[gr.f].l > 0;
+
+    // 1. chi = Pi X, C = V^dag X
+    const S *chi = X;
+    std::vector<long> goff(b.groups.size());
+    {
+        long o = 0;
+        for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+            goff[gi] = o;
+            o += (long)b.groups[gi].slots_h.size() * std::max(1, c->small[b.groups[gi].f].l);
+        }
+    }
+    if (any_small) {
+        chi = w.chi;
+        for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+            const auto &gr = b.groups[gi];
+            const Small &sm = c->small[gr.f];
+            Batch gb;
+            gb.n = (int)gr.slots_h.size();
+            gb.slots = gr.slots;
+            if (sm.l > 0) {
+                CHK(proj_dot<S>(c, sm.V, sm.l, X, gr, w.C + goff[gi], w.part));
+                CHK((proj_expand<S, S>(c, sm.V, sm.l, X, 1.0, w.chi, gr, w.C + goff[gi], -1.0)));
+            } else {
+                CHK((copy_fields<S, S>(c, gb, X, w.chi)));
+            }
+        }
+    }
+
+    // 2. Clenshaw recursion
+    const double al = 2.0 / ((1.0 - c->eps) * c->norm * c->norm);
+    const double be = (1.0 + c->eps) / (1.0 - c->eps);
+    const int n = c->npoly;
+    {
+        const S *in[1] = {chi};
+        const double2 cc[1] = {make_double2(c->coef[n], 0.0)};
+        CHK((lincomb<S, S>(c, b, w.B[0], 1, in, nullptr, cc, 0)));
+    }
+    int i1 = 0, i2 = -1;
+    for (int k = n - 1; k >= 1; --k) {
+        CHK(dslash_launch<S>(c, b, fgroup, w.B[i1], w.T, 1.0, true));
+        const int io = (i2 >= 0) ? i2 : (i1 + 1) % 3;
+        CHK(dslash_launch<S>(c, b, fgroup, w.T, w.B[io], 2.0 * al, true, chi, c->coef[k], w.B[i1], -2.0 * be,
+                             i2 >= 0 ? w.B[i2] : nullptr, -1.0));
+        i2 = i1;
+        i1 = io;
+    }
+    CHK(dslash_launch<S>(c, b, fgroup, w.B[i1], w.T, 1.0, true));
+    const int iz = (i2 >= 0) ? i2 : (i1 + 1) % 3;
+    CHK(dslash_launch<S>(c, b, fgroup, w.T, w.B[iz], al, true, chi, c->coef[0], w.B[i1], -be,
+                         i2 >= 0 ? w.B[i2] : nullptr, -1.0));
+
+    // 3. w = Q z
+    S *wout = any_small ? w.T : OUT;
+    CHK(dslash_launch<S>(c, b, fgroup, w.B[iz], wout, 1.0 / c->norm, true));
+
+    // 4. OUT = w - V (V^dag w) + V sgn C
+    if (any_small) {
+        for (size_t gi = 0; gi < b.groups.size(); ++gi) {
+            const auto &gr = b.groups[gi];
+            const Small &sm = c->small[gr.f];
+            const int ng = (int)gr.slots_h.size();
+            if (sm.l > 0) {
+                CHK(proj_dot<S>(c, sm.V, sm.l, wout, gr, w.D + goff[gi], w.part));
+                HIPCHK(launch_small_combine(w.C + goff[gi], w.D + goff[gi], sm.sgn, sm.l, ng, w.E + goff[gi],
+                                            c->stream));
+                CHK((proj_expand<S, S>(c, sm.V, sm.l, wout, 1.0, OUT, gr, w.E + goff[gi], 1.0)));
+            } else {
+                Batch gb;
+                gb.n = ng;
+                gb.slots = gr.slots;
+                CHK((copy_fields<S, S>(c, gb, wout, OUT)));
+            }
+        }
+    }
+    return OV_OK;
+}
+
+// ---------------------------------------------------------------- D(m)
+template <class S>
+struct DovBufs {
+    SignBufs<S> sb;
+    S *XG = nullptr, *Sv = nullptr;
+};
+
+template <class S>
+size_t dov_bufs_bytes(const ov_ctx *c, int nstore)
+{
+    return sign_bufs_bytes<S>(c, nstore) + 2 * align_up(field_bytes<S>(c) * nstore);
+}
+
+template <class S>
+int take_dov_bufs(ov_ctx *c, int nstore, DovBufs<S> &w)
+{
+    CHK(take_sign_bufs<S>(c, nstore, w.sb));
+    w.XG = ws_take<S>(c, field_elems(c) * nstore);
+    w.Sv = ws_take<S>(c, field_elems(c) * nstore);
+    if (!w.Sv) return fail(c, OV_ENOMEM, "workspace too small (internal)");
+    return OV_OK;
+}
+
+// Y = D(m) X or D(m)^dag X; ca = 1 + m/2, cb = 1 - m/2 per storage index.  Y may alias X.
+template <class S>
+int dov_batch(ov_ctx *c, const Batch &b, const int *fgroup, const double2 *ca, const double2 *cb, bool dagger,
+              const S *X, S *Y, DovBufs<S> &w)
+{
+    if (b.n == 0) return OV_OK;
+    const S *sin = X;
+    if (dagger) {
+        CHK((copy_fields<S, S>(c, b, X, w.XG, 1)));
+        sin = w.XG;
+    }
+    CHK(sign_batch<S>(c, b, fgroup, sin, w.Sv, w.sb));
+    // non-dagger: Y = ca X + cb gamma5 s ; dagger: Y = ca X + cb s
+    const S *in[2] = {X, w.Sv};
+    const double2 *cf[2] = {ca, cb};
+    return lincomb<S, S>(c, b, Y, 2, in, cf, nullptr, dagger ? 0 : 2);
+}
+
+int mass_coefs(ov_ctx *c, int n, const double *mass, const double2 **ca, const double2 **cb)
+{
+    std::vector<double> a(2 * n), bb(2 * n);
+    for (int j = 0; j < n; ++j) {
+        a[2 * j] = 1.0 + 0.5 * mass[j];
+        a[2 * j + 1] = 0.0;
+        bb[2 * j] = 1.0 - 0.5 * mass[j];
+        bb[2 * j + 1] = 0.0;
+    }
+    *ca = dev_cplx(c, a);
+    *cb = dev_cplx(c, bb);
+    if (!*ca || !*cb) return fail(c, OV_ENOMEM, "coefficient upload failed");
+    return OV_OK;
+}
+
+// ---------------------------------------------------------------- validation
+int check_ctx(ov_ctx *c)
+{
+    if (!c) return OV_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, OV_EHIP, "hipSetDevice(%d) failed", c->device);
+    return OV_OK;
+}
+
+int check_fields(ov_ctx *c, int nrhs, const int *field_of_rhs, std::vector<int> &grp)
+{
+    if (nrhs <= 0) return fail(c, OV_EINVAL, "nrhs must be positive (got %d)", nrhs);
+    if (nrhs > 4096) return fail(c, OV_EINVAL, "nrhs above 4096");
+    grp.assign(nrhs, 0);
+    for (int j = 0; j < nrhs; ++j) {
+        int f = field_of_rhs ? field_of_rhs[j] : 0;
+        if (f < 0 || f >= std::max(1, c->nfield))
+            return fail(c, OV_EINVAL, "field_of_rhs[%d] = %d outside [0, %d)", j, f, std::max(1, c->nfield));
+        grp[j] = f;
+    }
+    if (c->nfield == 0) return fail(c, OV_ESTATE, "ov_set_fields has not been called");
+    return OV_OK;
+}
+
+int check_prec(ov_ctx *c, int prec)
+{
+    if (prec != OV_FP64 && prec != OV_FP32 && prec != OV_BF16) return fail(c, OV_EINVAL, "unknown precision %d", prec);
+    return OV_OK;
+}
+
+std::vector<int> iota_vec(int n)
+{
+    std::vector<int> v(n);
+    for (int j = 0; j < n; ++j) v[j] = j;
+    return v;
+}
+
+// Chebyshev interpolant of y^{-1/2} on [eps, 1] at the n+1 Chebyshev-Gauss
+// nodes, in the variable t = (2y - 1 - eps)/(1 - eps) (Sec. 2: P(x) ~ x^{-1/2}).
+void cheb_interp(int n, double eps, std::vector<double> &c)
+{
+    const int m = n + 1;
+    std::vector<double> fy(m), th(m);
+    for (int j = 0; j < m; ++j) {
+        th[j] = M_PI * (j + 0.5) / m;
+        const double y = 0.5 * ((1.0 - eps) * std::cos(th[j]) + 1.0 + eps);
+        fy[j] = 1.0 / std::sqrt(y);
+    }
+    c.assign(m, 0.0);
+    for (int k = 0; k < m; ++k) {
+        double s = 0;
+        for (int j = 0; j < m; ++j) s += fy[j] * std::cos(k * th[j]);
+        c[k] = 2.0 * s / m;
+    }
+    c[0] *= 0.5;
+}
+
+int upload_phase(ov_ctx *c)
+{
+    const int Lt = c->L[3];
+    std::vector<cx<double>> h((size_t)c->nfield * Lt);
+    for (int f = 0; f < c->nfield; ++f)
+        for (int t = 0; t < Lt; ++t) {
+            const double th = c->q[f] * c->eta[f] * t;
+            h[(size_t)f * Lt + t] = {std::cos(th), std::sin(th)};
+        }
+    if (c->phase) dev_free(c, c->phase, 0);
+    c->phase = nullptr;
+    CHK(dev_alloc(c, (void **)&c->phase, h.size() * sizeof(cx<double>)));
+    HIPCHK(h2d(c, c->phase, h.data(), h.size() * sizeof(cx<double>)));
+    return OV_OK;
+}
+
+int count_nonfinite(ov_ctx *c, const void *p, long ndouble, int *bad)
+{
+    HIPCHK(hipMemsetAsync(c->d_count, 0, sizeof(int), c->stream));
+    HIPCHK(launch_count_nonfinite((const double *)p, ndouble, c->d_count, c->stream));
+    HIPCHK(hipMemcpyAsync(bad, c->d_count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return OV_OK;
+}
+
+// ---------------------------------------------------------------- typed API bodies
+template <class S>
+int api_dslash(ov_ctx *c, int op, int nrhs, const std::vector<int> &grp, const void *x, void *y)
+{
+    const size_t fb = align_up(field_bytes<S>(c) * nrhs);
+    CHK(ws_reserve(c, 2 * fb));
+    S *X = ws_take<S>(c, field_elems(c) * nrhs);
+    S *Y = ws_take<S>(c, field_elems(c) * nrhs);
+    Batch b;
+    CHK(make_batch(c, iota_vec(nrhs), grp, b));
+    const int *fg = dev_ints(c, grp);
+    HIPCHK(launch_pack_spinor<S>((const double2 *)x, X, (long)field_elems(c), nullptr, nrhs, c->g.V, c->g.Vp,
+                                 c->stream));
+    CHK(dslash_launch<S>(c, b, fg, X, Y, 1.0, op == OV_OP_HW));
+    HIPCHK(launch_unpack_spinor<S>(Y, (double2 *)y, (long)field_elems(c), nullptr, nrhs, c->g.V, c->g.Vp,
+                                   c->stream));
+    return OV_OK;
+}
+
+template <class S>
+int api_sign(ov_ctx *c, int nrhs, const std::vector<int> &grp, const void *x, void *y)
+{
+    CHK(ws_reserve(c, align_up(field_bytes<S>(c) * nrhs) + sign_bufs_bytes<S>(c, nrhs)));
+    S *X = ws_take<S>(c, field_elems(c) * nrhs);
+    SignBufs<S> w;
+    CHK(take_sign_bufs<S>(c, nrhs, w));
+    Batch b;
+    CHK(make_batch(c, iota_vec(nrhs), grp, b));
+    const int *fg = dev_ints(c, grp);
+    HIPCHK(launch_pack_spinor<S>((const double2 *)x, X, (long)field_elems(c), nullptr, nrhs, c->g.V, c->g.Vp,
+                                 c->stream));
+    CHK(sign_batch<S>(c, b, fg, X, X, w));
+    HIPCHK(launch_unpack_spinor<S>(X, (double2 *)y, (long)field_elems(c), nullptr, nrhs, c->g.V, c->g.Vp,
+                                   c->stream));
+    return OV_OK;
+}
+
+template <class S>
+int api_dov(ov_ctx *c, int nrhs, const std::vector<int> &grp, const double *mass, int dagger, const void *x,
+            void *y)
+{
+    CHK(ws_reserve(c, align_up(field_bytes<S>(c) * nrhs) + dov_bufs_bytes<S>(c, nrhs)));
+    S *X = ws_take<S>(c, field_elems(c) * nrhs);
+    DovBufs<S> w;
+    CHK(take_dov_bufs<S>(c, nrhs, w));
+    Batch b;
+    CHK(make_batch(c, iota_vec(nrhs), grp, b));
+    const int *fg = dev_ints(c, grp);
+    const double2 *ca, *cb;
+    CHK(mass_coefs(c, nrhs, mass, &ca, &cb));
+    HIPCHK(launch_pack_spinor<S>((const double2 *)x, X, (long)field_elems(c), nullptr, nrhs, c->g.V, c->g.Vp,
+                                 c->stream));
+    CHK(dov_batch<S>(c, b, fg, ca, cb, dagger != 0, X, X, w));
+    HIPCHK(launch_unpack_spinor<S>(X, (double2 *)y, (long)field_elems(c), nullptr, nrhs, c->g.V, c->g.Vp,
+                                   c->stream));
+    return OV_OK;
+}
+
+}  // namespace
+
+// ======================================================================== C ABI
+extern "C" {
+
+int ov_create(const int32_t L[4], const int32_t bc[4], double m_w, int device, ov_ctx **out)
+{
+    if (!out || !L || !bc) return OV_EINVAL;
+    *out = nullptr;
+    long V = 1;
+    for (int m = 0; m < 4; ++m) {
+        if (L[m] < 2 || L[m] > 4096) return OV_EINVAL;
+        if (bc[m] < 0 || bc[m] > 2) return OV_EINVAL;
+        V *= L[m];
+    }
+    if (V >= (1L << 31) / 64) return OV_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return OV_EHIP;
+    if (hipSetDevice(device) != hipSuccess) return OV_EHIP;
+    ov_ctx *c = new ov_ctx();
+    c->device = device;
+    for (int m = 0; m < 4; ++m) {
+        c->L[m] = L[m];
+        c->bc[m] = bc[m];
+    }
+    c->mw = m_w;
+    Geo &g = c->g;
+    g.Lx = L[0];
+    g.Ly = L[1];
+    g.Lz = L[2];
+    g.Lt = L[3];
+    g.V = (int)V;
+    g.Vp = (int)((V + 63) / 64 * 64);
+    g.Lxy = L[0] * L[1];
+    g.Lxyz = L[0] * L[1] * L[2];
+    for (int m = 0; m < 4; ++m) g.bcf[m] = bc[m] == 0 ? 1.0f : (bc[m] == 1 ? -1.0f : 0.0f);
+    c->stream = nullptr;   // the null stream until ov_set_stream names another one
+    if (dev_alloc(c, (void **)&c->d_count, 256) != OV_OK) {
+        delete c;
+        return OV_ENOMEM;
+    }
+    *out = c;
+    return OV_OK;
+}
+
+int ov_destroy(ov_ctx *c)
+{
+    if (!c) return OV_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->U64);
+    (void)hipFree(c->U32);
+    (void)hipFree(c->U16);
+    (void)hipFree(c->phase);
+    for (auto &s : c->small) {
+        (void)hipFree(s.V);
+        (void)hipFree(s.sgn);
+    }
+    for (auto &d : c->defl) (void)hipFree(d.W);
+    (void)hipFree(c->ws);
+    (void)hipFree(c->d_count);
+    for (auto &kv : c->icache) (void)hipFree(kv.second);
+    for (auto &kv : c->dcache) (void)hipFree(kv.second);
+    for (auto &kv : c->ccache) (void)hipFree(kv.second);
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    delete c;
+    return OV_OK;
+}
+
+int ov_set_stream(ov_ctx *c, void *stream)
+{
+    CHK(check_ctx(c));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->stream = (hipStream_t)stream;
+    return OV_OK;
+}
+
+const char *ov_last_error(const ov_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int ov_memory_used(const ov_ctx *c, int64_t *bytes)
+{
+    if (!c || !bytes) return OV_EINVAL;
+    *bytes = (int64_t)c->mem_bytes;
+    return OV_OK;
+}
+
+int ov_upload_gauge(ov_ctx *c, const void *U_dev)
+{
+    CHK(check_ctx(c));
+    if (!U_dev) return fail(c, OV_EINVAL, "null gauge pointer");
+    int bad = 0;
+    CHK(count_nonfinite(c, U_dev, 4L * c->g.V * 18, &bad));
+    if (bad) return fail(c, OV_ENAN, "gauge field holds %d non-finite numbers", bad);
+    const size_t n = 36ul * c->g.Vp;
+    if (!c->U64) {
+        CHK(dev_alloc(c, (void **)&c->U64, n * sizeof(double2)));
+        CHK(dev_alloc(c, (void **)&c->U32, n * sizeof(float2)));
+        CHK(dev_alloc(c, (void **)&c->U16, n * sizeof(uint32_t)));
+    }
+    HIPCHK(launch_pack_links<double2>((const double2 *)U_dev, c->U64, c->g.V, c->g.Vp, c->stream));
+    HIPCHK(launch_pack_links<float2>((const double2 *)U_dev, c->U32, c->g.V, c->g.Vp, c->stream));
+    HIPCHK(launch_pack_links<uint32_t>((const double2 *)U_dev, c->U16, c->g.V, c->g.Vp, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->have_gauge = true;
+    return OV_OK;
+}
+
+int ov_set_fields(ov_ctx *c, int nfield, const double *q, const double *eta)
+{
+    CHK(check_ctx(c));
+    if (nfield < 1 || nfield > 64 || !q || !eta) return fail(c, OV_EINVAL, "need 1 <= nfield <= 64 and q, eta");
+    for (int f = 0; f < nfield; ++f)
+        if (!std::isfinite(q[f]) || !std::isfinite(eta[f])) return fail(c, OV_ENAN, "non-finite q or eta");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->nfield = nfield;
+    c->q.assign(q, q + nfield);
+    c->eta.assign(eta, eta + nfield);
+    for (auto &s : c->small) {
+        dev_free(c, s.V, 16ul * 12 * c->g.Vp * s.l);
+        dev_free(c, s.sgn, 8ul * s.l);
+    }
+    for (auto &d : c->defl) dev_free(c, d.W, 16ul * 12 * c->g.Vp * d.k);
+    c->small.assign(nfield, Small());
+    c->defl.assign(nfield, Defl());
+    return upload_phase(c);
+}
+
+int ov_set_sign_params(ov_ctx *c, int n, double eps, double norm, const double *coeffs)
+{
+    CHK(check_ctx(c));
+    if (n < 1 || n > 100000) return fail(c, OV_EINVAL, "polynomial degree %d outside [1, 100000]", n);
+    if (!(eps > 0 && eps < 1)) return fail(c, OV_EINVAL, "eps must lie in (0, 1)");
+    if (norm <= 0) norm = std::fabs(4.0 + c->mw) + 4.0;
+    if (!std::isfinite(norm)) return fail(c, OV_ENAN, "non-finite norm");
+    c->npoly = n;
+    c->eps = eps;
+    c->norm = norm;
+    if (coeffs) {
+        c->coef.assign(coeffs, coeffs + n + 1);
+        for (double v : c->coef)
+            if (!std::isfinite(v)) return fail(c, OV_ENAN, "non-finite Chebyshev coefficient");
+    } else {
+        cheb_interp(n, eps, c->coef);
+    }
+    c->have_sign = true;
+    return OV_OK;
+}
+
+int ov_upload_eigvecs(ov_ctx *c, int field, int l, const void *V_dev, const double *lambda)
+{
+    CHK(check_ctx(c));
+    if (field < 0 || field >= c->nfield) return fail(c, OV_EINVAL, "field %d outside [0, %d)", field, c->nfield);
+    if (l < 0 || l > 256) return fail(c, OV_EINVAL, "small-space dimension %d outside [0, 256]", l);
+    if (l > 0 && (!V_dev || !lambda)) return fail(c, OV_EINVAL, "null V or lambda");
+    Small &sm = c->small[field];
+    HIPCHK(hipStreamSynchronize(c->stream));
+    dev_free(c, sm.V, 16ul * 12 * c->g.Vp * sm.l);
+    dev_free(c, sm.sgn, 8ul * sm.l);
+    sm = Small();
+    if (l == 0) return OV_OK;
+    int bad = 0;
+    CHK(count_nonfinite(c, V_dev, 24L * c->g.V * l, &bad));
+    if (bad) return fail(c, OV_ENAN, "small space holds non-finite numbers");
+    double2 *Vp = nullptr;
+    double *sg = nullptr;
+    CHK(dev_alloc(c, (void **)&Vp, 16ul * 12 * c->g.Vp * l));
+    CHK(dev_alloc(c, (void **)&sg, 8ul * l));
+    std::vector<double> sgn(l);
+    for (int i = 0; i < l; ++i) sgn[i] = lambda[i] >= 0 ? 1.0 : -1.0;
+    HIPCHK(h2d(c, sg, sgn.data(), 8ul * l));
+    HIPCHK(launch_pack_spinor<double2>((const double2 *)V_dev, Vp, (long)field_elems(c), nullptr, l, c->g.V,
+                                       c->g.Vp, c->stream));
+    // orthonormality check in FP64: G = V^dag V
+    CHK(ws_reserve(c, align_up((size_t)l * l * 16) + small_arrays_bytes(c, 48)));
+    double2 *G = ws_take<double2>(c, (size_t)l * l);
+    const long K = 12L * c->g.Vp;
+    const long nchunk = (K + proj_dot_chunk(K) - 1) / proj_dot_chunk(K);
+    double2 *part = ws_take<double2>(c, (size_t)nchunk * 48 * 256);
+    for (int j0 = 0; j0 < l; j0 += 48) {
+        const int nn = std::min(48, l - j0);
+        HIPCHK(launch_proj_dot<double2>(Vp, l, (long)field_elems(c), Vp + (long)j0 * field_elems(c),
+                                        (long)field_elems(c), nullptr, nn, c->g.Vp, 0, part, G + (long)j0 * l,
+                                        c->stream));
+    }
+    std::vector<double2> Gh((size_t)l * l);
+    HIPCHK(hipMemcpyAsync(Gh.data(), G, 16ul * l * l, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    double dev = 0;
+    for (int j = 0; j < l; ++j)
+        for (int i = 0; i < l; ++i) {
+            const double re = Gh[(size_t)j * l + i].x - (i == j ? 1.0 : 0.0), im = Gh[(size_t)j * l + i].y;
+            dev = std::max(dev, std::sqrt(re * re + im * im));
+        }
+    if (!(dev <= 1e-8)) {
+        dev_free(c, Vp, 16ul * 12 * c->g.Vp * l);
+        dev_free(c, sg, 8ul * l);
+        return fail(c, OV_EINVAL, "small space is not orthonormal: max |V^dag V - 1| = %.3e", dev);
+    }
+    sm.l = l;
+    sm.V = Vp;
+    sm.sgn = sg;
+    return OV_OK;
+}
+
+int ov_dslash(ov_ctx *c, int prec, int op, int nrhs, const int *field_of_rhs, const void *x, void *y)
+{
+    CHK(check_ctx(c));
+    CHK(check_prec(c, prec));
+    if (op != OV_OP_DW && op != OV_OP_HW) return fail(c, OV_EINVAL, "unknown operator %d", op);
+    if (!x || !y) return fail(c, OV_EINVAL, "null spinor pointer");
+    if (!c->have_gauge) return fail(c, OV_ESTATE, "no gauge field uploaded");
+    std::vector<int> grp;
+    CHK(check_fields(c, nrhs, field_of_rhs, grp));
+    if (prec == OV_FP64) return api_dslash<double2>(c, op, nrhs, grp, x, y);
+    if (prec == OV_FP32) return api_dslash<float2>(c, op, nrhs, grp, x, y);
+    return api_dslash<uint32_t>(c, op, nrhs, grp, x, y);
+}
+
+int ov_sign_apply(ov_ctx *c, int prec, int nrhs, const int *field_of_rhs, const void *x, void *y)
+{
+    CHK(check_ctx(c));
+    CHK(check_prec(c, prec));
+    if (!x || !y) return fail(c, OV_EINVAL, "null spinor pointer");
+    if (!c->have_gauge) return fail(c, OV_ESTATE, "no gauge field uploaded");
+    if (!c->have_sign) return fail(c, OV_ESTATE, "sign parameters not set");
+    std::vector<int> grp;
+    CHK(check_fields(c, nrhs, field_of_rhs, grp));
+    if (prec == OV_FP64) return api_sign<double2>(c, nrhs, grp, x, y);
+    if (prec == OV_FP32) return api_sign<float2>(c, nrhs, grp, x, y);
+    return api_sign<uint32_t>(c, nrhs, grp, x, y);
+}
+
+int ov_dov_apply(ov_ctx *c, int prec, int nrhs, const int *field_of_rhs, const double *mass, int dagger,
+                 const void *x, void *y)
+{
+    CHK(check_ctx(c));
+    CHK(check_prec(c, prec));
+    if (!x || !y || !mass) return fail(c, OV_EINVAL, "null pointer argument");
+    if (!c->have_gauge) return fail(c, OV_ESTATE, "no gauge field uploaded");
+    if (!c->have_sign) return fail(c, OV_ESTATE, "sign parameters not set");
+    std::vector<int> grp;
+    CHK(check_fields(c, nrhs, field_of_rhs, grp));
+    for (int j = 0; j < nrhs; ++j)
+        if (!std::isfinite(mass[j])) return fail(c, OV_ENAN, "non-finite mass");
+    if (prec == OV_FP64) return api_dov<double2>(c, nrhs, grp, mass, dagger, x, y);
+    if (prec == OV_FP32) return api_dov<float2>(c, nrhs, grp, mass, dagger, x, y);
+    return api_dov<uint32_t>(c, nrhs, grp, mass, dagger, x, y);
+}
+
+int ov_prof_enable(ov_ctx *c, int on)
+{
+    CHK(check_ctx(c));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->prof_on = on != 0;
+    c->recs.clear();
+    c->ev_used = 0;
+    return OV_OK;
+}
+
+int ov_prof_query(ov_ctx *c, const char *cls, long *launches, double *total_ms, double *bytes)
+{
+    CHK(check_ctx(c));
+    int k = -1;
+    for (int i = 0; i < PC_N; ++i)
+        if (cls && std::strcmp(cls, kProfNames[i]) == 0) k = i;
+    if (k < 0) return fail(c, OV_EINVAL, "unknown kernel class");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    long cnt = 0;
+    double ms = 0, by = 0;
+    for (auto &r : c->recs) {
+        if (r.cls != k) continue;
+        float t = 0;
+        HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+        ++cnt;
+        ms += t;
+        by += r.bytes;
+    }
+    if (launches) *launches = cnt;
+    if (total_ms) *total_ms = ms;
+    if (bytes) *bytes = by;
+    return OV_OK;
+}
+
+int ov_set_tuning(ov_ctx *c, int prec, int rhs_per_thread, int block)
+{
+    CHK(check_ctx(c));
+    CHK(check_prec(c, prec));
+    if (rhs_per_thread != 1 && rhs_per_thread != 2 && rhs_per_thread != 4 && rhs_per_thread != 8)
+        return fail(c, OV_EINVAL, "rhs_per_thread must be 1, 2, 4 or 8");
+    if (block < 64 || block > 256 || block % 64) return fail(c, OV_EINVAL, "block must be 64, 128, 192 or 256");
+    c->nr[prec] = rhs_per_thread;
+    c->block[prec] = block;
+    return OV_OK;
+}
+
+int ov_get_tuning(ov_ctx *c, int prec, int *rhs_per_thread, int *block)
+{
+    CHK(check_ctx(c));
+    CHK(check_prec(c, prec));
+    if (rhs_per_thread) *rhs_per_thread = c->nr[prec];
+    if (block) *block = c->block[prec];
+    return OV_OK;
+}
+
+}  // extern "C"
+
+
+// ======================================================================== solver
+namespace {
+
+// Per-RHS scalars of the inner CG, indexed by storage index.
+struct CgScalars {
+    double *rr, *rr_new, *stop, *red;
+    double2 *pAp, *ap, *an, *beta, *one;
+    int *active;
+    double2 *dpart;
+};
+
+template <class S>
+size_t cg_inner_bytes(const ov_ctx *c, int n)
+{
+    return 5 * align_up(field_bytes<S>(c) * n) + dov_bufs_bytes<S>(c, n);
+}
+
+// FP64 true residual R = RHS - D^dag D X on batch b (uses the FP64 D_ov buffers).
+int residual64(ov_ctx *c, const Batch &b, const int *fg, const double2 *ca, const double2 *cb, const double2 *RHS,
+               const double2 *X, double2 *R, double2 *tmp, DovBufs<double2> &w)
+{
+    CHK(dov_batch<double2>(c, b, fg, ca, cb, false, X, tmp, w));
+    CHK(dov_batch<double2>(c, b, fg, ca, cb, true, tmp, tmp, w));
+    const double2 *in[2] = {RHS, tmp};
+    const double2 cc[2] = {make_double2(1, 0), make_double2(-1, 0)};
+    return lincomb<double2, double2>(c, b, R, 2, in, nullptr, cc, 0);
+}
+
+// squared norms of the entries of b (by storage index) into host vector
+int norms2(ov_ctx *c, const Batch &b, const double2 *X, CgScalars &s, int nstore, std::vector<double> &out)
+{
+    HIPCHK((launch_dot<double2, double2>(X, (long)field_elems(c), X, (long)field_elems(c), b.slots, b.n, c->g.Vp, 0,
+                                         s.dpart, s.pAp, b.slots, c->stream)));
+    std::vector<double2> h(nstore);
+    HIPCHK(hipMemcpyAsync(h.data(), s.pAp, 16ul * nstore, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    out.assign(nstore, 0.0);
+    for (int j : b.slots_h) out[j] = h[j].x;
+    return OV_OK;
+}
+
+// Inner CG on A e = r0 (r0 given in R64, FP64), e returned in E (precision S),
+// for the RHS of batch bo.  Iteration counts per storage index added to iters.
+template <class S>
+int inner_cg(ov_ctx *c, const Batch &bo, const std::vector<int> &grp, const int *fg, const double2 *ca,
+             const double2 *cb, const double *mass, const double2 *R64, S *E, S *r, S *p, S *Ap, S *Dp,
+             DovBufs<S> &w, CgScalars &s, int nstore, double inner_tol, int budget, bool use_defl,
+             std::vector<int> &iters, int &total)
+{
+    const long fe = (long)field_elems(c);
+    // r = R ; e = 0 (or the deflation guess)
+    CHK((copy_fields<double2, S>(c, bo, R64, r)));
+    const double2 zero = make_double2(0, 0);
+    {
+        const S *in[1] = {r};
+        CHK((lincomb<S, S>(c, bo, E, 1, in, nullptr, &zero, 0)));
+    }
+    bool did_defl = false;
+    if (use_defl) {
+        for (auto &gr : bo.groups) {
+            const Defl &d = c->defl[gr.f];
+            if (d.k == 0) continue;
+            const int ng = (int)gr.slots_h.size();
+            // C = W^dag R (FP64), E_coef = C / Lambda(m)
+            double2 *C = w.sb.C, *Ec = w.sb.E;
+            CHK(proj_dot<double2>(c, d.W, d.k, R64, gr, C, w.sb.part));
+            std::vector<double> inv((size_t)ng * d.k);
+            for (int j = 0; j < ng; ++j) {
+                const double m = mass[gr.slots_h[j]];
+                for (int i = 0; i < d.k; ++i) {
+                    const double lam = (1 - 0.5 * m) * (1 - 0.5 * m) * d.a[i] + 2 * m * (1 - 0.5 * m) * d.b[i] + m * m;
+                    inv[(size_t)j * d.k + i] = lam > 0 ? 1.0 / lam : 0.0;
+                }
+            }
+            const double *invd = dev_doubles(c, inv);
+            if (!invd) return fail(c, OV_ENOMEM, "deflation weights upload failed");
+            HIPCHK(launch_mul_coef(C, invd, d.k, ng, Ec, c->stream));
+            CHK((proj_expand<S, S>(c, d.W, d.k, (const S *)nullptr, 0.0, E, gr, Ec, 1.0)));
+            did_defl = true;
+        }
+        if (did_defl) {   // r = R - A e0
+            CHK(dov_batch<S>(c, bo, fg, ca, cb, false, E, Dp, w));
+            CHK(dov_batch<S>(c, bo, fg, ca, cb, true, Dp, Ap, w));
+            const S *in[2] = {r, Ap};
+            const double2 cc[2] = {make_double2(1, 0), make_double2(-1, 0)};
+            CHK((lincomb<S, S>(c, bo, r, 2, in, nullptr, cc, 0)));
+        }
+    }
+    // p = r ; rr = |r|^2 ; stop = inner_tol^2 |R|^2
+    int nb = 0;
+    {
+        const S *in[1] = {r};
+        CHK((lincomb<S, S>(c, bo, p, 1, in, nullptr, nullptr, 0, s.red, &nb)));
+        HIPCHK(launch_reduce_r(s.red, nb, bo.n, s.rr, bo.slots, c->stream));
+    }
+    std::vector<double> rr0(nstore, 0.0), stop(nstore, 0.0);
+    {
+        std::vector<double> h(nstore);
+        HIPCHK(hipMemcpyAsync(h.data(), s.rr, 8ul * nstore, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int j : bo.slots_h) {
+            rr0[j] = h[j];
+            stop[j] = inner_tol * inner_tol * h[j];
+        }
+    }
+    std::vector<int> act(nstore, 0);
+    for (int j : bo.slots_h) act[j] = rr0[j] > 0 ? 1 : 0;
+    HIPCHK(h2d(c, s.stop, stop.data(), 8ul * nstore));
+    HIPCHK(h2d(c, s.active, act.data(), 4ul * nstore));
+
+    std::vector<int> cur;
+    for (int j : bo.slots_h)
+        if (act[j]) cur.push_back(j);
+    while (!cur.empty() && total < budget) {
+        Batch bi;
+        CHK(make_batch(c, cur, grp, bi));
+        // Ap = D^dag D p
+        CHK(dov_batch<S>(c, bi, fg, ca, cb, false, p, Dp, w));
+        CHK(dov_batch<S>(c, bi, fg, ca, cb, true, Dp, Ap, w));
+        HIPCHK((launch_dot<S, S>(p, fe, Ap, fe, bi.slots, bi.n, c->g.Vp, 0, s.dpart, s.pAp, bi.slots, c->stream)));
+        HIPCHK(launch_cg_alpha(s.rr, s.pAp, s.active, nstore, s.ap, s.an, c->stream));
+        {   // e += alpha p ; r -= alpha Ap (with |r|^2)
+            const S *in1[2] = {E, p};
+            const double2 *cf1[2] = {s.one, s.ap};
+            CHK((lincomb<S, S>(c, bi, E, 2, in1, cf1, nullptr, 0)));
+            const S *in2[2] = {r, Ap};
+            const double2 *cf2[2] = {s.one, s.an};
+            CHK((lincomb<S, S>(c, bi, r, 2, in2, cf2, nullptr, 0, s.red, &nb)));
+            HIPCHK(launch_reduce_r(s.red, nb, bi.n, s.rr_new, bi.slots, c->stream));
+        }
+        HIPCHK(launch_cg_beta(s.rr_new, s.rr, s.active, s.stop, nstore, s.beta, c->stream));
+        {   // p = r + beta p
+            const S *in[2] = {r, p};
+            const double2 *cf[2] = {s.one, s.beta};
+            CHK((lincomb<S, S>(c, bi, p, 2, in, cf, nullptr, 0)));
+        }
+        for (int j : cur) iters[j] += 1;
+        total += 1;
+        HIPCHK(hipMemcpyAsync(act.data(), s.active, 4ul * nstore, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        std::vector<int> nxt;
+        for (int j : cur)
+            if (act[j]) nxt.push_back(j);
+        cur.swap(nxt);
+    }
+    return OV_OK;
+}
+
+template <class S>
+int api_cg(ov_ctx *c, int nrhs, const std::vector<int> &grp, const double *mass, const void *b_dev, void *x_dev,
+           const ov_cg_opts &o, ov_cg_rhs_report *rep)
+{
+    const int n = nrhs;
+    const size_t f64 = align_up(field_bytes<double2>(c) * n);
+    const size_t regionA = std::max(dov_bufs_bytes<double2>(c, n) + f64, cg_inner_bytes<S>(c, n));
+    const size_t scal = 16 * align_up(16ul * n) + 2 * align_up(16ul * (8192 + n));
+    CHK(ws_reserve(c, 4 * f64 + regionA + scal));
+    double2 *B64 = ws_take<double2>(c, field_elems(c) * n);
+    double2 *X64 = ws_take<double2>(c, field_elems(c) * n);
+    double2 *RHS = ws_take<double2>(c, field_elems(c) * n);
+    double2 *R64 = ws_take<double2>(c, field_elems(c) * n);
+    CgScalars s;
+    s.rr = ws_take<double>(c, n);
+    s.rr_new = ws_take<double>(c, n);
+    s.stop = ws_take<double>(c, n);
+    s.pAp = ws_take<double2>(c, n);
+    s.ap = ws_take<double2>(c, n);
+    s.an = ws_take<double2>(c, n);
+    s.beta = ws_take<double2>(c, n);
+    s.one = ws_take<double2>(c, n);
+    s.active = ws_take<int>(c, n);
+    // partial sums: a launch over n RHS uses at most max(8192, n) blocks in total
+    s.red = ws_take<double>(c, 8192 + (size_t)n);
+    s.dpart = ws_take<double2>(c, 8192 + (size_t)n);
+    const size_t regA_start = c->ws_top;
+    {
+        std::vector<double2> ones(n, make_double2(1, 0));
+        HIPCHK(h2d(c, s.one, ones.data(), 16ul * n));
+    }
+    // FP64 view of region A
+    double2 *T64 = ws_take<double2>(c, field_elems(c) * n);
+    DovBufs<double2> w64;
+    CHK(take_dov_bufs<double2>(c, n, w64));
+    // precision-S view of region A (aliases the FP64 view)
+    c->ws_top = regA_start;
+    S *E = ws_take<S>(c, field_elems(c) * n), *r = ws_take<S>(c, field_elems(c) * n);
+    S *p = ws_take<S>(c, field_elems(c) * n), *Ap = ws_take<S>(c, field_elems(c) * n);
+    S *Dp = ws_take<S>(c, field_elems(c) * n);
+    DovBufs<S> wS;
+    CHK(take_dov_bufs<S>(c, n, wS));
+
+    Batch ball;
+    CHK(make_batch(c, iota_vec(n), grp, ball));
+    const int *fg = dev_ints(c, grp);
+    const double2 *ca, *cb;
+    CHK(mass_coefs(c, n, mass, &ca, &cb));
+
+    HIPCHK(launch_pack_spinor<double2>((const double2 *)b_dev, B64, (long)field_elems(c), nullptr, n, c->g.V,
+                                       c->g.Vp, c->stream));
+    HIPCHK(launch_pack_spinor<double2>((const double2 *)x_dev, X64, (long)field_elems(c), nullptr, n, c->g.V,
+                                       c->g.Vp, c->stream));
+    // RHS = D^dag b
+    CHK(dov_batch<double2>(c, ball, fg, ca, cb, true, B64, RHS, w64));
+    std::vector<double> rhs2, x2;
+    CHK(norms2(c, ball, RHS, s, n, rhs2));
+    CHK(norms2(c, ball, X64, s, n, x2));
+    for (int j = 0; j < n; ++j)
+        if (!std::isfinite(rhs2[j]) || !std::isfinite(x2[j])) return fail(c, OV_ENAN, "non-finite source or guess");
+    bool xzero = true;
+    for (int j = 0; j < n; ++j) xzero = xzero && x2[j] == 0.0;
+    if (xzero)
+        CHK((copy_fields<double2, double2>(c, ball, RHS, R64)));
+    else
+        CHK(residual64(c, ball, fg, ca, cb, RHS, X64, R64, T64, w64));
+
+    std::vector<int> iters(n, 0), restarts(n, 0);
+    std::vector<double> relres(n, 0.0);
+    int total = 0;
+    int rounds = 0;
+    for (;;) {
+        std::vector<double> res2;
+        CHK(norms2(c, ball, R64, s, n, res2));
+        std::vector<int> todo;
+        for (int j = 0; j < n; ++j) {
+            if (!std::isfinite(res2[j])) return fail(c, OV_ENAN, "non-finite residual for RHS %d", j);
+            relres[j] = rhs2[j] > 0 ? std::sqrt(res2[j] / rhs2[j]) : 0.0;
+            if (relres[j] > o.tol) todo.push_back(j);
+        }
+        if (todo.empty() || rounds >= o.max_restarts || total >= o.maxiter) break;
+        Batch bo;
+        CHK(make_batch(c, todo, grp, bo));
+        CHK(inner_cg<S>(c, bo, grp, fg, ca, cb, mass, R64, E, r, p, Ap, Dp, wS, s, n, o.inner_tol, o.maxiter,
+                        o.use_deflation != 0, iters, total));
+        // X += e (through R64 as an FP64 staging buffer), then the new true residual
+        CHK((copy_fields<S, double2>(c, bo, E, R64)));
+        {
+            const double2 *in[2] = {X64, R64};
+            CHK((lincomb<double2, double2>(c, bo, X64, 2, in, nullptr, nullptr, 0)));
+        }
+        CHK(residual64(c, ball, fg, ca, cb, RHS, X64, R64, T64, w64));
+        for (int j : todo) restarts[j] += 1;
+        ++rounds;
+    }
+    HIPCHK(launch_unpack_spinor<double2>(X64, (double2 *)x_dev, (long)field_elems(c), nullptr, n, c->g.V, c->g.Vp,
+                                         c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    bool ok = true;
+    for (int j = 0; j < n; ++j) {
+        const bool conv = relres[j] <= o.tol;
+        ok = ok && conv;
+        if (rep) {
+            rep[j].iters = iters[j];
+            rep[j].restarts = restarts[j];
+            rep[j].relres = relres[j];
+            rep[j].status = conv ? OV_OK : OV_ENOCONV;
+        }
+    }
+    if (!ok) return fail(c, OV_ENOCONV, "CG did not reach tol = %.3e within the iteration budget", o.tol);
+    return OV_OK;
+}
+
+// ---------------------------------------------------------------- adjoint
+int api_backward(ov_ctx *c, int f, const void *x_dev, const void *g_dev, void *gU_dev, double *geta, void *gx_dev,
+                 int K)
+{
+    using S = double2;
+    const int n = c->npoly;
+    const long fe = (long)field_elems(c);
+    const int nseg = (n + K - 1) / K;
+    const int nb_fin = (c->g.V + 255) / 256;
+    // fields: X, Gv, chi, z, wbar, zbar, t1, t2, bb[3], seg[K], ckpt[2*nseg], sign bufs
+    const size_t nf = 11 + (size_t)K + 2 * nseg;
+    const size_t need = nf * align_up(field_bytes<S>(c)) + align_up(36ul * c->g.Vp * 16) + align_up(8ul * nb_fin) +
+                        sign_bufs_bytes<S>(c, 1);
+    CHK(ws_reserve(c, need));
+    S *X = ws_take<S>(c, fe), *Gv = ws_take<S>(c, fe), *chi = ws_take<S>(c, fe), *z = ws_take<S>(c, fe);
+    S *wbar = ws_take<S>(c, fe), *zbar = ws_take<S>(c, fe), *t1 = ws_take<S>(c, fe), *t2 = ws_take<S>(c, fe);
+    S *bb[3] = {ws_take<S>(c, fe), ws_take<S>(c, fe), ws_take<S>(c, fe)};
+    std::vector<S *> seg(K), ck(2 * nseg);
+    for (int i = 0; i < K; ++i) seg[i] = ws_take<S>(c, fe);
+    for (int i = 0; i < 2 * nseg; ++i) ck[i] = ws_take<S>(c, fe);
+    double2 *G = ws_take<double2>(c, 36ul * c->g.Vp);
+    double *epart = ws_take<double>(c, nb_fin);
+    SignBufs<S> w;
+    CHK(take_sign_bufs<S>(c, 1, w));
+    if (!epart) return fail(c, OV_ENOMEM, "workspace too small (internal)");
+
+    std::vector<int> grp = {f};
+    Batch b;
+    CHK(make_batch(c, {0}, grp, b));
+    const int *fg = dev_ints(c, grp);
+    const Small &sm = c->small[f];
+    const double al = 2.0 / ((1.0 - c->eps) * c->norm * c->norm);
+    const double be = (1.0 + c->eps) / (1.0 - c->eps);
+    const double kap = 2.0 / (1.0 - c->eps);
+    const double invN = 1.0 / c->norm;
+    const double2 zero = make_double2(0, 0);
+
+    HIPCHK(launch_pack_spinor<S>((const double2 *)x_dev, X, fe, nullptr, 1, c->g.V, c->g.Vp, c->stream));
+    HIPCHK(launch_pack_spinor<S>((const double2 *)g_dev, Gv, fe, nullptr, 1, c->g.V, c->g.Vp, c->stream));
+    if (gx_dev) {   // gx = s g
+        CHK(sign_batch<S>(c, b, fg, Gv, t1, w));
+        HIPCHK(launch_unpack_spinor<S>(t1, (double2 *)gx_dev, fe, nullptr, 1, c->g.V, c->g.Vp, c->stream));
+    }
+    if (!gU_dev && !geta) return OV_OK;
+
+    // chi = Pi x
+    if (sm.l > 0) {
+        CHK(proj_dot<S>(c, sm.V, sm.l, X, b.groups[0], w.C, w.part));
+        CHK((proj_expand<S, S>(c, sm.V, sm.l, X, 1.0, chi, b.groups[0], w.C, -1.0)));
+    } else {
+        CHK((copy_fields<S, S>(c, b, X, chi)));
+    }
+    // One Clenshaw step k: out = c_k chi + 2T b1 - b2 (b2 may be NULL); uses t1.
+    auto step = [&](int k, const S *b1, const S *b2, S *out) -> int {
+        if (k == n) {
+            const S *in[1] = {chi};
+            const double2 cc[1] = {make_double2(c->coef[n], 0)};
+            return lincomb<S, S>(c, b, out, 1, in, nullptr, cc, 0);
+        }
+        CHK(dslash_launch<S>(c, b, fg, b1, t1, 1.0, true));
+        return dslash_launch<S>(c, b, fg, t1, out, 2.0 * al, true, chi, c->coef[k], b1, -2.0 * be, b2, -1.0);
+    };
+    // forward pass: keep (b_{top+1}, b_{top+2}) of every segment [s*K+1, min((s+1)K, n)]
+    {
+        const S *b1 = nullptr, *b2 = nullptr;
+        int i1 = 0;
+        for (int k = n; k >= 1; --k) {
+            const int sgi = (k - 1) / K;
+            const int top = std::min((sgi + 1) * K, n);
+            if (k == top) {   // checkpoint the inputs of this segment
+                S *c1 = ck[2 * sgi], *c2 = ck[2 * sgi + 1];
+                const double2 one = make_double2(1, 0);
+                if (b1) { const S *in[1] = {b1}; CHK((lincomb<S, S>(c, b, c1, 1, in, nullptr, &one, 0))); }
+                else { const S *in[1] = {chi}; CHK((lincomb<S, S>(c, b, c1, 1, in, nullptr, &zero, 0))); }
+                if (b2) { const S *in[1] = {b2}; CHK((lincomb<S, S>(c, b, c2, 1, in, nullptr, &one, 0))); }
+                else { const S *in[1] = {chi}; CHK((lincomb<S, S>(c, b, c2, 1, in, nullptr, &zero, 0))); }
+            }
+            S *out = bb[i1];
+            if (b2 == bb[0] || b2 == bb[1] || b2 == bb[2]) out = (S *)b2;
+            CHK(step(k, b1, b2, out));
+            b2 = b1;
+            b1 = out;
+            i1 = (out == bb[0]) ? 1 : (out == bb[1] ? 2 : 0);
+            if (b1 == bb[i1] || b2 == bb[i1]) i1 = (i1 + 1) % 3;
+            if (b1 == bb[i1] || b2 == bb[i1]) i1 = (i1 + 1) % 3;
+        }
+        // z = c_0 chi + T b_1 - b_2
+        CHK(dslash_launch<S>(c, b, fg, b1, t1, 1.0, true));
+        CHK(dslash_launch<S>(c, b, fg, t1, z, al, true, chi, c->coef[0], b1, -be, b2, -1.0));
+    }
+    // wbar = Pi g ; zbar = Q wbar
+    if (sm.l > 0) {
+        CHK(proj_dot<S>(c, sm.V, sm.l, Gv, b.groups[0], w.C, w.part));
+        CHK((proj_expand<S, S>(c, sm.V, sm.l, Gv, 1.0, wbar, b.groups[0], w.C, -1.0)));
+    } else {
+        CHK((copy_fields<S, S>(c, b, Gv, wbar)));
+    }
+    CHK(dslash_launch<S>(c, b, fg, wbar, zbar, invN, true));
+
+    HIPCHK(hipMemsetAsync(G, 0, 36ul * c->g.Vp * 16, c->stream));
+    auto force = [&](const S *u, const S *v, double coef) -> int {
+        ForceArgs fa{u, v, G, coef, c->g};
+        int pi = prof_begin(c);
+        HIPCHK(launch_force(fa, c->stream));
+        prof_end(c, pi, PC_FORCE, (double)c->g.V * (4 * 192.0 + 2 * 576.0));
+        return OV_OK;
+    };
+    // Re<wbar, dQ z>
+    CHK(force(wbar, z, invN));
+
+    // adjoint vectors bb_k = T_k(T) zbar, upward; pairs with b_{k+1}
+    // bb_0 = zbar (kept in bbv[0]), bb_1 = T zbar
+    S *bbv[3] = {bb[0], bb[1], bb[2]};
+    {
+        const double2 one = make_double2(1, 0);
+        const S *in[1] = {zbar};
+        CHK((lincomb<S, S>(c, b, bbv[0], 1, in, nullptr, &one, 0)));
+        CHK(dslash_launch<S>(c, b, fg, zbar, t1, 1.0, true));
+        CHK(dslash_launch<S>(c, b, fg, t1, bbv[1], al, true, zbar, -be));
+    }
+    int cur = 1, prev = 0;   // indices into bbv of bb_k and bb_{k-1}
+    for (int sgi = 0; sgi < nseg; ++sgi) {
+        const int lo = sgi * K + 1, top = std::min((sgi + 1) * K, n);
+        // replay b_top .. b_lo into seg[k - lo]
+        {
+            const S *b1 = ck[2 * sgi], *b2 = ck[2 * sgi + 1];
+            const bool fresh = (top == n);
+            for (int k = top; k >= lo; --k) {
+                S *out = seg[k - lo];
+                if (k == n) {
+                    CHK(step(k, nullptr, nullptr, out));
+                } else {
+                    const bool b2zero = fresh && (k == n - 1);
+                    CHK(step(k, b1, b2zero ? nullptr : b2, out));
+                }
+                b2 = b1;
+                b1 = out;
+            }
+        }
+        // b_{k+1} for k in [lo, top]: seg[k+1-lo] when k+1 <= top, else the checkpoint b_{top+1}
+        for (int k = lo; k <= top; ++k) {
+            if (k == n) break;               // b_{n+1} = 0
+            const S *bk1 = (k + 1 <= top) ? seg[k + 1 - lo] : ck[2 * sgi];
+            if (k == 1) {
+                // Re<zbar, dT b_1> = kap (Re<zbar, dQ Q b_1> + Re<Q zbar, dQ b_1>)
+                const S *b1v = seg[0];
+                CHK(dslash_launch<S>(c, b, fg, b1v, t2, 1.0, true));   // N Q b_1
+                CHK(force(zbar, t2, kap * invN * invN));
+                CHK(dslash_launch<S>(c, b, fg, zbar, t2, 1.0, true));  // N Q zbar
+                CHK(force(t2, b1v, kap * invN * invN));
+            }
+            // 2 Re<bb_k, dT b_{k+1}> = 2 kap (Re<bb_k, dQ Q b_{k+1}> + Re<Q bb_k, dQ b_{k+1}>)
+            CHK(dslash_launch<S>(c, b, fg, bk1, t2, 1.0, true));
+            CHK(force(bbv[cur], t2, 2.0 * kap * invN * invN));
+            CHK(dslash_launch<S>(c, b, fg, bbv[cur], t1, 1.0, true));
+            CHK(force(t1, bk1, 2.0 * kap * invN * invN));
+            // bb_{k+1} = 2T bb_k - bb_{k-1} = 2 al H t1 - 2 be bb_k - bb_{k-1}, into bb_{k-1}'s buffer
+            CHK(dslash_launch<S>(c, b, fg, t1, bbv[prev], 2.0 * al, true, bbv[cur], -2.0 * be, bbv[prev], -1.0));
+            std::swap(cur, prev);
+        }
+    }
+    // gradients w.r.t. the base links and eta
+    const cx<double> *prow = c->phase + (size_t)f * c->g.Lt;
+    HIPCHK(launch_force_finish(G, c->U64, prow, c->q[f], c->g, (double2 *)gU_dev, epart, nb_fin, c->stream));
+    std::vector<double> eh(nb_fin);
+    HIPCHK(hipMemcpyAsync(eh.data(), epart, 8ul * nb_fin, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (geta) {
+        double sum = 0;
+        for (double v : eh) sum += v;
+        *geta = sum;
+    }
+    return OV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ov_deflated_cg(ov_ctx *c, int nrhs, const int *field_of_rhs, const double *mass, const void *b_dev,
+                   void *x_dev, const ov_cg_opts *opts, ov_cg_rhs_report *report)
+{
+    CHK(check_ctx(c));
+    if (!b_dev || !x_dev || !mass || !opts) return fail(c, OV_EINVAL, "null pointer argument");
+    if (!c->have_gauge) return fail(c, OV_ESTATE, "no gauge field uploaded");
+    if (!c->have_sign) return fail(c, OV_ESTATE, "sign parameters not set");
+    CHK(check_prec(c, opts->inner_prec));
+    if (!(opts->tol >= 0) || !(opts->inner_tol > 0 && opts->inner_tol < 1) || opts->maxiter < 0 ||
+        opts->max_restarts < 0)
+        return fail(c, OV_EINVAL, "bad CG options");
+    std::vector<int> grp;
+    CHK(check_fields(c, nrhs, field_of_rhs, grp));
+    for (int j = 0; j < nrhs; ++j)
+        if (!std::isfinite(mass[j])) return fail(c, OV_ENAN, "non-finite mass");
+    if (opts->inner_prec == OV_FP64) return api_cg<double2>(c, nrhs, grp, mass, b_dev, x_dev, *opts, report);
+    if (opts->inner_prec == OV_FP32) return api_cg<float2>(c, nrhs, grp, mass, b_dev, x_dev, *opts, report);
+    return api_cg<uint32_t>(c, nrhs, grp, mass, b_dev, x_dev, *opts, report);
+}
+
+int ov_upload_deflation(ov_ctx *c, int field, int k, const void *W_dev)
+{
+    CHK(check_ctx(c));
+    if (field < 0 || field >= c->nfield) return fail(c, OV_EINVAL, "field %d outside [0, %d)", field, c->nfield);
+    if (k < 0 || k > 256) return fail(c, OV_EINVAL, "deflation dimension %d outside [0, 256]", k);
+    if (!c->have_gauge || !c->have_sign) return fail(c, OV_ESTATE, "upload the gauge field and set the sign first");
+    Defl &d = c->defl[field];
+    HIPCHK(hipStreamSynchronize(c->stream));
+    dev_free(c, d.W, 16ul * 12 * c->g.Vp * d.k);
+    d = Defl();
+    if (k == 0) return OV_OK;
+    if (!W_dev) return fail(c, OV_EINVAL, "null deflation basis");
+    int bad = 0;
+    CHK(count_nonfinite(c, W_dev, 24L * c->g.V * k, &bad));
+    if (bad) return fail(c, OV_ENAN, "deflation basis holds non-finite numbers");
+    double2 *W = nullptr;
+    CHK(dev_alloc(c, (void **)&W, 16ul * 12 * c->g.Vp * k));
+    HIPCHK(launch_pack_spinor<double2>((const double2 *)W_dev, W, (long)field_elems(c), nullptr, k, c->g.V, c->g.Vp,
+                                       c->stream));
+    // a_i = |D_ov w_i|^2, b_i = Re<w_i, D_ov w_i>, in batches of 16 (FP64)
+    const int nbt = std::min(k, 16);
+    CHK(ws_reserve(c, align_up(field_bytes<double2>(c) * nbt) + dov_bufs_bytes<double2>(c, nbt) +
+                          2 * align_up(16ul * nbt) + align_up(16ul * nbt * 8192)));
+    double2 *Y = ws_take<double2>(c, field_elems(c) * nbt);
+    DovBufs<double2> w;
+    CHK(take_dov_bufs<double2>(c, nbt, w));
+    double2 *o1 = ws_take<double2>(c, nbt), *o2 = ws_take<double2>(c, nbt);
+    double2 *part = ws_take<double2>(c, (size_t)nbt * 8192);
+    std::vector<double> zeros(nbt, 0.0);
+    const double2 *ca, *cb;
+    CHK(mass_coefs(c, nbt, zeros.data(), &ca, &cb));
+    d.a.assign(k, 0.0);
+    d.b.assign(k, 0.0);
+    for (int i0 = 0; i0 < k; i0 += nbt) {
+        const int nn = std::min(nbt, k - i0);
+        std::vector<int> gv(nbt, field);
+        Batch b;
+        CHK(make_batch(c, iota_vec(nn), gv, b));
+        const int *fg = dev_ints(c, gv);
+        const double2 *Wi = W + (long)i0 * field_elems(c);
+        CHK(dov_batch<double2>(c, b, fg, ca, cb, false, Wi, Y, w));
+        HIPCHK((launch_dot<double2, double2>(Y, (long)field_elems(c), Y, (long)field_elems(c), nullptr, nn, c->g.Vp,
+                                             0, part, o1, nullptr, c->stream)));
+        HIPCHK((launch_dot<double2, double2>(Wi, (long)field_elems(c), Y, (long)field_elems(c), nullptr, nn,
+                                             c->g.Vp, 0, part, o2, nullptr, c->stream)));
+        std::vector<double2> h1(nn), h2(nn);
+        HIPCHK(hipMemcpyAsync(h1.data(), o1, 16ul * nn, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(h2.data(), o2, 16ul * nn, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < nn; ++i) {
+            d.a[i0 + i] = h1[i].x;
+            d.b[i0 + i] = h2[i].x;
+        }
+    }
+    d.k = k;
+    d.W = W;
+    return OV_OK;
+}
+
+int ov_sign_backward(ov_ctx *c, int field, const void *x_dev, const void *g_dev, void *gU_dev, double *geta,
+                     void *gx_dev, int ckpt_every)
+{
+    CHK(check_ctx(c));
+    if (field < 0 || field >= c->nfield) return fail(c, OV_EINVAL, "field %d outside [0, %d)", field, c->nfield);
+    if (!x_dev || !g_dev) return fail(c, OV_EINVAL, "null x or g");
+    if (ckpt_every < 1) return fail(c, OV_EINVAL, "ckpt_every must be >= 1");
+    if (!c->have_gauge || !c->have_sign) return fail(c, OV_ESTATE, "upload the gauge field and set the sign first");
+    return api_backward(c, field, x_dev, g_dev, gU_dev, geta, gx_dev, std::min(ckpt_every, c->npoly));
+}
+
+int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
+{
+    CHK(check_ctx(c));
+    CHK(check_prec(c, prec));
+    if (!c->have_gauge || c->nfield == 0) return fail(c, OV_ESTATE, "upload the gauge field and fields first");
+    if (nrhs < 1 || nrhs > 4096) return fail(c, OV_EINVAL, "nrhs outside [1, 4096]");
+    // Times the fused Clenshaw launch (dslash + epilogue) for every candidate
+    // on synthetic data already in the workspace; keeps the fastest.
+    auto run = [&](auto tag) -> int {
+        using S = decltype(tag);
+        const size_t fb = align_up(field_bytes<S>(c) * nrhs);
+        CHK(ws_reserve(c, 5 * fb));
+        S *x = ws_take<S>(c, field_elems(c) * nrhs), *y = ws_take<S>(c, field_elems(c) * nrhs);
+        S *e1 = ws_take<S>(c, field_elems(c) * nrhs), *e2 = ws_take<S>(c, field_elems(c) * nrhs);
+        S *e3 = ws_take<S>(c, field_elems(c) * nrhs);
+        std::vector<int> grp(nrhs, 0);
+        for (int j = 0; j < nrhs; ++j) grp[j] = j % c->nfield;
+        Batch b;
+        CHK(make_batch(c, iota_vec(nrhs), grp, b));
+        const int *fg = dev_ints(c, grp);
+        hipEvent_t e0, e9;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e9));
+        const int nrs[4] = {1, 2, 4, 8}, blks[3] = {64, 128, 256};
+        float best = 1e30f;
+        int bnr = c->nr[prec], bbl = c->block[prec];
+        const bool was = c->prof_on;
+        c->prof_on = false;
+        for (int nr : nrs) {
+            if (nr > 1 && nr / 2 >= nrhs) continue;
+            if (prec == OV_FP64 && nr == 8) continue;
+            for (int bl : blks) {
+                c->nr[prec] = nr;
+                c->block[prec] = bl;
+                for (int rep = 0; rep < 2; ++rep)
+                    CHK(dslash_launch<S>(c, b, fg, x, y, 1.0, true, e1, 0.5, e2, -0.5, e3, -1.0));
+                HIPCHK(hipEventRecord(e0, c->stream));
+                const int reps = 5;
+                for (int rep = 0; rep < reps; ++rep)
+                    CHK(dslash_launch<S>(c, b, fg, x, y, 1.0, true, e1, 0.5, e2, -0.5, e3, -1.0));
+                HIPCHK(hipEventRecord(e9, c->stream));
+                HIPCHK(hipEventSynchronize(e9));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e9));
+                if (ms < best) {
+                    best = ms;
+                    bnr = nr;
+                    bbl = bl;
+                }
+            }
+        }
+        c->prof_on = was;
+        c->nr[prec] = bnr;
+        c->block[prec] = bbl;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e9);
+        if (cache_path) {
+            FILE *fp = std::fopen(cache_path, "a");
+            if (fp) {
+                std::fprintf(fp,
+                             "{\"arch\": \"gfx950\", \"L\": [%d, %d, %d, %d], \"prec\": %d, \"nrhs\": %d, "
+                             "\"rhs_per_thread\": %d, \"block\": %d, \"ms_per_launch\": %.6f}\n",
+                             c->L[0], c->L[1], c->L[2], c->L[3], prec, nrhs, bnr, bbl, best / 5.0);
+                std::fclose(fp);
+            }
+        }
+        return OV_OK;
+    };
+    if (prec == OV_FP64) return run(double2{});
+    if (prec == OV_FP32) return run(float2{});
+    return run(uint32_t{});
+}
+
+}  // extern "C"

@@ -1,0 +1,337 @@
+// Streaming kernels of the overlap path: layout packing, precision
+// conversion, linear combinations (with an optional fused squared norm),
+// batched inner products with a fixed-order two-stage reduction, and the
+// per-RHS CG scalar updates.  All of them are HBM-bound; they read and write
+// whole planes with consecutive lanes on consecutive sites.
+#include "ov_device.h"
+#include "ov_internal.h"
+
+namespace ov {
+
+// ---------------------------------------------------------------- packing
+// canonical complex128 [n][V][4][3]  <->  planes [slot][12][Vp]
+template <class S>
+__global__ void k_pack_spinor(const double2 *__restrict__ in, S *__restrict__ out, long fstride,
+                              const int *slots, int n, int V, int Vp)
+{
+    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (site >= Vp || j >= n) return;
+    const int s = slots ? slots[j] : j;
+    S *o = out + (long)s * fstride;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        cx<double> v = {0.0, 0.0};
+        if (site < V) {
+            double2 w = in[((long)j * V + site) * 12 + k];
+            v = {w.x, w.y};
+        }
+        stc<double>(o, (long)k * Vp + site, v);
+    }
+}
+
+template <class S>
+__global__ void k_unpack_spinor(const S *__restrict__ in, double2 *__restrict__ out, long fstride,
+                                const int *slots, int n, int V, int Vp)
+{
+    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (site >= V || j >= n) return;
+    const int s = slots ? slots[j] : j;
+    const S *p = in + (long)s * fstride;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        cx<double> v = ldc<double>(p, (long)k * Vp + site);
+        out[((long)j * V + site) * 12 + k] = make_double2(v.x, v.y);
+    }
+}
+
+// canonical [4][V][3][3]  ->  planes [4][9][Vp]
+template <class S>
+__global__ void k_pack_links(const double2 *__restrict__ in, S *__restrict__ out, int V, int Vp)
+{
+    const int site = blockIdx.x * blockDim.x + threadIdx.x;
+    const int mu = blockIdx.y;
+    if (site >= Vp) return;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        cx<double> v = {0.0, 0.0};
+        if (site < V) {
+            double2 w = in[((long)mu * V + site) * 9 + k];
+            v = {w.x, w.y};
+        }
+        stc<double>(out, (long)(mu * 9 + k) * Vp + site, v);
+    }
+}
+
+// Count of non-finite doubles in a buffer (result accumulated atomically).
+__global__ void k_count_nonfinite(const double *__restrict__ p, long n, int *count)
+{
+    int bad = 0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        bad += !isfinite(p[i]);
+    if (bad) atomicAdd(count, bad);
+}
+
+// ---------------------------------------------------------------- lincomb
+// out_s = sum_j coef_j(s) * G_j in_j,s   (G_j = gamma5 if bit j of g5mask)
+// optionally red[s][blk] = sum |out_s|^2 over this block's elements.
+template <class SI, class SO>
+__global__ __launch_bounds__(256) void k_lincomb(LcArgs<SI, SO> a)
+{
+    const int j = blockIdx.y;
+    if (j >= a.n) return;
+    const int s = a.slots ? a.slots[j] : j;
+    cx<double> cf[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        if (t < a.nin) {
+            const double2 c = a.coef[t] ? a.coef[t][a.coef_by_slot ? s : j] : a.cconst[t];
+            cf[t] = {c.x, c.y};
+        }
+    }
+    const long ne = 12L * a.Vp;
+    const long half = 6L * a.Vp;
+    double nrm = 0.0;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < ne; e += (long)gridDim.x * blockDim.x) {
+        cx<double> v = {0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            if (t < a.nin) {
+                cx<double> x = ldc<double>(a.in[t] + (long)s * a.istride[t], e);
+                if (((a.g5mask >> t) & 1) && e >= half) x = {-x.x, -x.y};
+                cfma(v, cf[t], x);
+            }
+        }
+        stc<double>(a.out + (long)s * a.ostride, e, v);
+        if (a.red) nrm += v.x * v.x + v.y * v.y;
+    }
+    if (a.red) {
+        __shared__ double sh[256];
+        sh[threadIdx.x] = nrm;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) a.red[(long)j * gridDim.x + blockIdx.x] = sh[0];
+    }
+}
+
+// ---------------------------------------------------------------- dot
+// part[j][blk] = sum over block of conj(G a_s) b_s
+template <class SA, class SB>
+__global__ __launch_bounds__(256) void k_dot(const SA *__restrict__ a, long astride, const SB *__restrict__ b,
+                                             long bstride, const int *slots, int n, int Vp, int g5a,
+                                             double2 *part)
+{
+    const int j = blockIdx.y;
+    if (j >= n) return;
+    const int s = slots ? slots[j] : j;
+    const long ne = 12L * Vp, half = 6L * Vp;
+    cx<double> acc = {0.0, 0.0};
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < ne; e += (long)gridDim.x * blockDim.x) {
+        cx<double> x = ldc<double>(a + (long)s * astride, e);
+        if (g5a && e >= half) x = {-x.x, -x.y};
+        cfmac(acc, x, ldc<double>(b + (long)s * bstride, e));
+    }
+    __shared__ double shr[256], shi[256];
+    shr[threadIdx.x] = acc.x;
+    shi[threadIdx.x] = acc.y;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            shr[threadIdx.x] += shr[threadIdx.x + w];
+            shi[threadIdx.x] += shi[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long)j * gridDim.x + blockIdx.x] = make_double2(shr[0], shi[0]);
+}
+
+// out[slot(j)] = sum_b part[j][b] in a fixed order (one workgroup per j)
+__global__ void k_reduce_c(const double2 *__restrict__ part, int nb, int n, double2 *out, const int *oslots)
+{
+    const int j = blockIdx.x;
+    if (j >= n) return;
+    __shared__ double shr[256], shi[256];
+    double r = 0, i = 0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        double2 v = part[(long)j * nb + b];
+        r += v.x;
+        i += v.y;
+    }
+    shr[threadIdx.x] = r;
+    shi[threadIdx.x] = i;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            shr[threadIdx.x] += shr[threadIdx.x + w];
+            shi[threadIdx.x] += shi[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[oslots ? oslots[j] : j] = make_double2(shr[0], shi[0]);
+}
+
+__global__ void k_reduce_r(const double *__restrict__ part, int nb, int n, double *out, const int *oslots)
+{
+    const int j = blockIdx.x;
+    if (j >= n) return;
+    __shared__ double sh[256];
+    double r = 0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) r += part[(long)j * nb + b];
+    sh[threadIdx.x] = r;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[oslots ? oslots[j] : j] = sh[0];
+}
+
+// ---------------------------------------------------------------- CG scalars
+// alpha_j = active_j ? rr_j / Re(pAp_j) : 0 ; stored as complex coefficients
+// +alpha (for x += alpha p) and -alpha (for r -= alpha Ap).
+__global__ void k_cg_alpha(const double *rr, const double2 *pAp, const int *active, int n,
+                           double2 *alpha_pos, double2 *alpha_neg)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double al = 0.0;
+    if (active[j] && pAp[j].x > 0.0) al = rr[j] / pAp[j].x;
+    alpha_pos[j] = make_double2(al, 0.0);
+    alpha_neg[j] = make_double2(-al, 0.0);
+}
+
+// beta_j = rr_new / rr_old; rr_old <- rr_new; deactivate when rr_new <= stop_j.
+__global__ void k_cg_beta(const double *rr_new, double *rr, int *active, const double *stop, int n,
+                          double2 *beta)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double be = 0.0;
+    if (active[j]) {
+        be = rr[j] > 0.0 ? rr_new[j] / rr[j] : 0.0;
+        rr[j] = rr_new[j];
+        if (!(rr_new[j] > stop[j])) active[j] = 0;
+    }
+    beta[j] = make_double2(be, 0.0);
+}
+
+// ---------------------------------------------------------------- launchers
+static inline int nblocks_for(long ne, int n)
+{
+    // about 8k workgroups in total, at least one per RHS, at most one per 256 elements
+    long want = 8192 / (n > 0 ? n : 1);
+    long maxb = (ne + 255) / 256;
+    if (want < 1) want = 1;
+    if (want > maxb) want = maxb;
+    return (int)want;
+}
+
+template <class S>
+hipError_t launch_pack_spinor(const double2 *in, S *out, long fstride, const int *slots, int n, int V,
+                              int Vp, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    dim3 grid((Vp + 255) / 256, n);
+    hipLaunchKernelGGL((k_pack_spinor<S>), grid, dim3(256), 0, st, in, out, fstride, slots, n, V, Vp);
+    return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_unpack_spinor(const S *in, double2 *out, long fstride, const int *slots, int n, int V,
+                                int Vp, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    dim3 grid((V + 255) / 256, n);
+    hipLaunchKernelGGL((k_unpack_spinor<S>), grid, dim3(256), 0, st, in, out, fstride, slots, n, V, Vp);
+    return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_pack_links(const double2 *in, S *out, int V, int Vp, hipStream_t st)
+{
+    dim3 grid((Vp + 255) / 256, 4);
+    hipLaunchKernelGGL((k_pack_links<S>), grid, dim3(256), 0, st, in, out, V, Vp);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(const double *p, long n, int *count, hipStream_t st)
+{
+    long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(nb), dim3(256), 0, st, p, n, count);
+    return hipGetLastError();
+}
+
+template <class SI, class SO>
+hipError_t launch_lincomb(LcArgs<SI, SO> a, hipStream_t st, int *nblk_out)
+{
+    if (a.n <= 0) return hipSuccess;
+    const int nb = nblocks_for(12L * a.Vp, a.n);
+    if (nblk_out) *nblk_out = nb;
+    hipLaunchKernelGGL((k_lincomb<SI, SO>), dim3(nb, a.n), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+int lincomb_blocks(int Vp, int n) { return nblocks_for(12L * Vp, n); }
+
+template <class SA, class SB>
+hipError_t launch_dot(const SA *a, long astride, const SB *b, long bstride, const int *slots, int n, int Vp,
+                      int g5a, double2 *part, double2 *out, const int *oslots, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int nb = nblocks_for(12L * Vp, n);
+    hipLaunchKernelGGL((k_dot<SA, SB>), dim3(nb, n), dim3(256), 0, st, a, astride, b, bstride, slots, n, Vp,
+                       g5a, part);
+    hipLaunchKernelGGL(k_reduce_c, dim3(n), dim3(256), 0, st, part, nb, n, out, oslots);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_r(const double *part, int nb, int n, double *out, const int *oslots, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_r, dim3(n), dim3(256), 0, st, part, nb, n, out, oslots);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_alpha(const double *rr, const double2 *pAp, const int *active, int n, double2 *ap,
+                           double2 *an, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_alpha, dim3((n + 63) / 64), dim3(64), 0, st, rr, pAp, active, n, ap, an);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_beta(const double *rr_new, double *rr, int *active, const double *stop, int n,
+                          double2 *beta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cg_beta, dim3((n + 63) / 64), dim3(64), 0, st, rr_new, rr, active, stop, n, beta);
+    return hipGetLastError();
+}
+
+#define OV_INST_S(S)                                                                                   \
+    template hipError_t launch_pack_spinor<S>(const double2 *, S *, long, const int *, int, int, int,  \
+                                              hipStream_t);                                            \
+    template hipError_t launch_unpack_spinor<S>(const S *, double2 *, long, const int *, int, int, int, \
+                                                hipStream_t);                                          \
+    template hipError_t launch_pack_links<S>(const double2 *, S *, int, int, hipStream_t);
+OV_INST_S(double2)
+OV_INST_S(float2)
+OV_INST_S(uint32_t)
+
+#define OV_INST_2(A, B)                                                                                   \
+    template hipError_t launch_lincomb<A, B>(LcArgs<A, B>, hipStream_t, int *);                           \
+    template hipError_t launch_dot<A, B>(const A *, long, const B *, long, const int *, int, int, int,   \
+                                         double2 *, double2 *, const int *, hipStream_t);
+OV_INST_2(double2, double2)
+OV_INST_2(float2, float2)
+OV_INST_2(uint32_t, uint32_t)
+OV_INST_2(double2, float2)
+OV_INST_2(float2, double2)
+OV_INST_2(double2, uint32_t)
+OV_INST_2(uint32_t, double2)
+
+}  // namespace ov

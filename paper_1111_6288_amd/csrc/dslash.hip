@@ -1,0 +1,236 @@
+// Wilson dslash / H_w for a batch of right-hand sides, with an optional
+// fused linear epilogue used by the Clenshaw recursion of the sign function.
+//
+//   y_r = a * G (D_w x_r)  +  c1 e1_r + c2 e2_r + c3 e3_r          (own site)
+//   D_w x(s) = (4 + m_w) x(s)
+//        - 1/2 sum_mu [ (1 - gamma_mu) U~_mu(s) x(s+mu) + (1 + gamma_mu) U~_mu(s-mu)^dag x(s-mu) ]
+//   G = gamma5 for H_w = gamma5 D_w (Sec. 2), identity for D_w.
+//
+// U~_0 carries the background-field phase exp(i q eta t) of the RHS's field
+// group (Sec. 4, eq. (3)), applied to the projected half spinor so that the
+// links stay shared by every RHS in the batch.  Hops that wrap around the
+// lattice take the boundary multiplier (+1, -1, 0; Dirichlet hops are skipped).
+//
+// Spin projection uses the chiral basis: each (1 -/+ gamma_mu) has rank two,
+// so the neighbour spinor is reduced to a half spinor h0, h1 (2 x 3 complex),
+// multiplied by the 3x3 link and expanded back.  One thread owns one site and
+// NR right-hand sides: the link is loaded once and applied to all NR spinors.
+#include "ov_device.h"
+#include "ov_internal.h"
+#include "spin.h"
+
+namespace ov {
+
+template <class S, class R>
+__device__ __forceinline__ void load_link(const S *__restrict__ U, int mu, int Vp, int s, cx<R> (&u)[3][3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) u[a][b] = ldc<R>(U, (long)(mu * 9 + a * 3 + b) * Vp + s);
+}
+
+template <class S, class R>
+__device__ __forceinline__ void load_spinor(const S *__restrict__ x, int Vp, int s, cx<R> (&p)[4][3])
+{
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p[sp][c] = ldc<R>(x, (long)(sp * 3 + c) * Vp + s);
+}
+
+// One direction, both hops, for all NR right-hand sides of this thread.
+template <int MU, int NR, class S, class R>
+__device__ __forceinline__ void hop_dir(const DsArgs<S> &a, int site, int cmu, int Lmu, int stride,
+                                        const long (&off)[NR], const bool (&act)[NR],
+                                        const cx<R> (&ph)[NR], cx<R> (&acc)[NR][4][3])
+{
+    const int Vp = a.g.Vp;
+    // forward hop: -1/2 (1 - gamma_mu) U~_mu(s) x(s + mu)
+    {
+        const bool wrap = (cmu == Lmu - 1);
+        const int j = wrap ? site - (Lmu - 1) * stride : site + stride;
+        const R bf = wrap ? (R)a.g.bcf[MU] : (R)1;
+        if (bf != (R)0) {
+            cx<R> u[3][3];
+            load_link<S, R>(a.U, MU, Vp, site, u);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (!act[r]) continue;
+                cx<R> p[4][3], h[2][3], g[2][3];
+                load_spinor<S, R>(a.x + off[r], Vp, j, p);
+                project<MU, -1>(p, h);
+                if (MU == 0 || wrap) {
+                    cx<R> f = (MU == 0) ? cscale(ph[r], bf) : cmk(bf, (R)0);
+#pragma unroll
+                    for (int k = 0; k < 2; ++k)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) h[k][c] = cmul(f, h[k][c]);
+                }
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int aa = 0; aa < 3; ++aa) {
+                        cx<R> t = cmul(u[aa][0], h[k][0]);
+                        cfma(t, u[aa][1], h[k][1]);
+                        cfma(t, u[aa][2], h[k][2]);
+                        g[k][aa] = t;
+                    }
+                expand_add<MU, -1>(acc[r], g);
+            }
+        }
+    }
+    // backward hop: -1/2 (1 + gamma_mu) U~_mu(s - mu)^dag x(s - mu)
+    {
+        const bool wrap = (cmu == 0);
+        const int j = wrap ? site + (Lmu - 1) * stride : site - stride;
+        const R bf = wrap ? (R)a.g.bcf[MU] : (R)1;
+        if (bf != (R)0) {
+            cx<R> u[3][3];
+            load_link<S, R>(a.U, MU, Vp, j, u);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (!act[r]) continue;
+                cx<R> p[4][3], h[2][3], g[2][3];
+                load_spinor<S, R>(a.x + off[r], Vp, j, p);
+                project<MU, +1>(p, h);
+                if (MU == 0 || wrap) {
+                    cx<R> f = (MU == 0) ? cmk(ph[r].x * bf, -ph[r].y * bf) : cmk(bf, (R)0);
+#pragma unroll
+                    for (int k = 0; k < 2; ++k)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) h[k][c] = cmul(f, h[k][c]);
+                }
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int aa = 0; aa < 3; ++aa) {
+                        cx<R> t = cmulc(u[0][aa], h[k][0]);
+                        cfmac(t, u[1][aa], h[k][1]);
+                        cfmac(t, u[2][aa], h[k][2]);
+                        g[k][aa] = t;
+                    }
+                expand_add<MU, +1>(acc[r], g);
+            }
+        }
+    }
+}
+
+// Workgroups are handed to the 8 XCDs round-robin; remap so that each XCD
+// receives a contiguous run of sites, which keeps stencil neighbours in the
+// same XCD's L2.  nblk must be a multiple of 8 (the launcher pads).
+__device__ __forceinline__ int xcd_block(int b, int nblk)
+{
+    const int per = nblk >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+template <class S, int NR, bool HW, bool EPI>
+__global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
+{
+    using R = typename StoreT<S>::real;
+    const Geo &g = a.g;
+    const int blk = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    const int site = blk * blockDim.x + threadIdx.x;
+    if (site >= g.V) return;
+    const int j0 = blockIdx.y * NR;
+
+    int rem = site;
+    const int xc = rem % g.Lx; rem /= g.Lx;
+    const int yc = rem % g.Ly; rem /= g.Ly;
+    const int zc = rem % g.Lz;
+    const int tc = rem / g.Lz;
+
+    long off[NR];
+    bool act[NR];
+    cx<R> ph[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int j = j0 + r;
+        act[r] = j < a.n;
+        const int jj = act[r] ? j : j0;
+        const int s = a.slots ? a.slots[jj] : jj;
+        off[r] = (long)s * a.fstride;
+        const int grp = a.fgroup ? a.fgroup[s] : 0;
+        const cx<double> p = a.phase[grp * g.Lt + tc];
+        ph[r] = cmk((R)p.x, (R)p.y);
+    }
+
+    cx<R> acc[NR][4][3];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[r][sp][c] = cmk((R)0, (R)0);
+
+    hop_dir<0, NR, S, R>(a, site, xc, g.Lx, 1, off, act, ph, acc);
+    hop_dir<1, NR, S, R>(a, site, yc, g.Ly, g.Lx, off, act, ph, acc);
+    hop_dir<2, NR, S, R>(a, site, zc, g.Lz, g.Lxy, off, act, ph, acc);
+    hop_dir<3, NR, S, R>(a, site, tc, g.Lt, g.Lxyz, off, act, ph, acc);
+
+    const R diag = (R)a.diag, sc = (R)a.a;
+    const R c1 = (R)a.c1, c2 = (R)a.c2, c3 = (R)a.c3;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (!act[r]) continue;
+        cx<R> p[4][3];
+        load_spinor<S, R>(a.x + off[r], g.Vp, site, p);
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cx<R> v = cmk(diag * p[sp][c].x - (R)0.5 * acc[r][sp][c].x,
+                              diag * p[sp][c].y - (R)0.5 * acc[r][sp][c].y);
+                R s = (HW && sp >= 2) ? -sc : sc;
+                v = cscale(v, s);
+                const long k = (long)(sp * 3 + c) * g.Vp + site;
+                if (EPI) {
+                    if (a.e1) { cx<R> e = ldc<R>(a.e1 + off[r], k); v.x = fma(c1, e.x, v.x); v.y = fma(c1, e.y, v.y); }
+                    if (a.e2) { cx<R> e = ldc<R>(a.e2 + off[r], k); v.x = fma(c2, e.x, v.x); v.y = fma(c2, e.y, v.y); }
+                    if (a.e3) { cx<R> e = ldc<R>(a.e3 + off[r], k); v.x = fma(c3, e.x, v.x); v.y = fma(c3, e.y, v.y); }
+                }
+                stc<R>(a.y + off[r], k, v);
+            }
+    }
+}
+
+template <class S, int NR>
+static hipError_t launch_nr(const DsArgs<S> &a, bool hw, bool epi, int block, hipStream_t st)
+{
+    int nbx = (a.g.V + block - 1) / block;
+    DsArgs<S> b = a;
+    b.xcd_remap = 0;
+    if (nbx >= 64) {          // pad to a multiple of 8 for the XCD remap
+        nbx = (nbx + 7) & ~7;
+        b.xcd_remap = 1;
+    }
+    dim3 grid(nbx, (a.n + NR - 1) / NR);
+    if (epi)
+        hipLaunchKernelGGL((k_dslash<S, NR, true, true>), grid, dim3(block), 0, st, b);
+    else if (hw)
+        hipLaunchKernelGGL((k_dslash<S, NR, true, false>), grid, dim3(block), 0, st, b);
+    else
+        hipLaunchKernelGGL((k_dslash<S, NR, false, false>), grid, dim3(block), 0, st, b);
+    return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_dslash(const DsArgs<S> &a, bool hw, bool epi, int nr, int block, hipStream_t st)
+{
+    if (a.n <= 0) return hipSuccess;
+    if (block < 64 || block > 256 || (block & 63)) return hipErrorInvalidValue;
+    switch (nr) {
+    case 1: return launch_nr<S, 1>(a, hw, epi, block, st);
+    case 2: return launch_nr<S, 2>(a, hw, epi, block, st);
+    case 4: return launch_nr<S, 4>(a, hw, epi, block, st);
+    case 8: return launch_nr<S, 8>(a, hw, epi, block, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_dslash<double2>(const DsArgs<double2> &, bool, bool, int, int, hipStream_t);
+template hipError_t launch_dslash<float2>(const DsArgs<float2> &, bool, bool, int, int, hipStream_t);
+template hipError_t launch_dslash<uint32_t>(const DsArgs<uint32_t> &, bool, bool, int, int, hipStream_t);
+
+}  // namespace ov

@@ -1,0 +1,100 @@
+// Internal declarations shared by the libov translation units: kernel
+// argument blocks and launcher entry points.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ov_device.h"
+
+namespace ov {
+
+// ---------------------------------------------------------------- dslash
+template <class S>
+struct DsArgs {
+    const S *x;              // input batch (planes), read at the 8 neighbours and the own site
+    S *y;                    // output batch, must not alias x
+    long fstride;            // storage elements between consecutive fields
+    const S *U;              // links [4][9][Vp]
+    const int *slots;        // storage index of batch entry j (NULL: j)
+    int n;                   // batch size
+    const int *fgroup;       // field group of a storage index (NULL: 0)
+    const cx<double> *phase; // [nfield][Lt] background phase exp(i q eta t)
+    Geo g;
+    double diag;             // 4 + m_w
+    double a;                // scale of G D_w x
+    const S *e1, *e2, *e3;   // epilogue inputs at the own site (same fstride), NULL if unused
+    double c1, c2, c3;
+    int xcd_remap;           // set by the launcher
+};
+
+template <class S>
+hipError_t launch_dslash(const DsArgs<S> &a, bool hw, bool epi, int nr, int block, hipStream_t st);
+
+// ---------------------------------------------------------------- lincomb
+template <class SI, class SO>
+struct LcArgs {
+    const SI *in[3];
+    long istride[3];
+    int nin;                 // 1..3 terms
+    int g5mask;              // bit t: apply gamma5 to term t
+    const double2 *coef[3];  // per-RHS complex coefficients (NULL: use cconst)
+    int coef_by_slot;        // index coef by storage index instead of batch position
+    double2 cconst[3];
+    SO *out;
+    long ostride;
+    const int *slots;
+    int n;
+    int Vp;
+    double *red;             // optional partial |out|^2 [n][nblk]
+};
+
+template <class SI, class SO>
+hipError_t launch_lincomb(LcArgs<SI, SO> a, hipStream_t st, int *nblk_out);
+int lincomb_blocks(int Vp, int n);
+
+template <class SA, class SB>
+hipError_t launch_dot(const SA *a, long astride, const SB *b, long bstride, const int *slots, int n, int Vp,
+                      int g5a, double2 *part, double2 *out, const int *oslots, hipStream_t st);
+hipError_t launch_reduce_r(const double *part, int nb, int n, double *out, const int *oslots, hipStream_t st);
+hipError_t launch_cg_alpha(const double *rr, const double2 *pAp, const int *active, int n, double2 *ap,
+                           double2 *an, hipStream_t st);
+hipError_t launch_cg_beta(const double *rr_new, double *rr, int *active, const double *stop, int n,
+                          double2 *beta, hipStream_t st);
+
+template <class S>
+hipError_t launch_pack_spinor(const double2 *in, S *out, long fstride, const int *slots, int n, int V, int Vp,
+                              hipStream_t st);
+template <class S>
+hipError_t launch_unpack_spinor(const S *in, double2 *out, long fstride, const int *slots, int n, int V, int Vp,
+                                hipStream_t st);
+template <class S>
+hipError_t launch_pack_links(const double2 *in, S *out, int V, int Vp, hipStream_t st);
+hipError_t launch_count_nonfinite(const double *p, long n, int *count, hipStream_t st);
+
+// ---------------------------------------------------------------- projection
+long proj_dot_chunk(long K);
+template <class S>
+hipError_t launch_proj_dot(const double2 *V, int l, long vstride, const S *X, long xstride, const int *slots,
+                           int n, int Vp, int g5x, double2 *part, double2 *C, hipStream_t st);
+template <class SX, class SY>
+hipError_t launch_proj_expand(const double2 *V, int l, long vstride, const SX *X, long xstride, double alpha,
+                              SY *Y, long ystride, const int *slots, int n, int Vp, const double2 *E, double beta,
+                              hipStream_t st);
+hipError_t launch_small_combine(const double2 *C, const double2 *D, const double *sgn, int l, int n, double2 *E,
+                                hipStream_t st);
+hipError_t launch_mul_coef(const double2 *C, const double *w, int l, int n, double2 *E, hipStream_t st);
+
+// ---------------------------------------------------------------- backward
+struct ForceArgs {
+    const double2 *u;        // planes [12][Vp]
+    const double2 *v;        // planes [12][Vp]
+    double2 *G;              // force accumulator [4][9][Vp] (phased links)
+    double coef;             // weight of Re<u, dQ v>, includes 1/norm
+    Geo g;
+};
+hipError_t launch_force(const ForceArgs &a, hipStream_t st);
+hipError_t launch_force_finish(const double2 *G, const double2 *U, const cx<double> *phase_row, double q,
+                               Geo g, double2 *gU_canon, double *eta_part, int nb, hipStream_t st);
+
+}  // namespace ov

@@ -1,0 +1,291 @@
+// Small-space projection (Sec. 2, Fig. 1: the lowest eigenvectors of H_w
+// are treated exactly).  Two complex FP64 contractions with a long inner
+// dimension K = 12 Vp:
+//
+//   proj_dot     C[j][i] = sum_k conj(V_i[k]) (G X_j)[k]        (V^dag X)
+//   proj_expand  Y_j[k]  = alpha X_j[k] + sum_i V_i[k] E[j][i]   (X + V E)
+//
+// V is FP64 (planes [l][12][Vp], the spinor layout).  X and Y may be stored in
+// FP64, FP32 or BF16; every product and sum is FP64.  The dot runs split-K:
+// each workgroup reduces one K-chunk to a partial l x n block, then a fixed-
+// order pass sums the partials (deterministic).  Both use the matrix cores
+// (v_mfma_f64_16x16x4f64) with 16x16 tiles of (vector, RHS).
+#include "ov_device.h"
+#include "ov_internal.h"
+
+namespace ov {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// --------------------------------------------------------------- V^dag X (MFMA)
+// Workgroup = 4 waves; it owns one K-chunk.  Wave w owns vector tiles
+// w, w+4, ... (up to MT tiles) and all RHS tiles (up to NT).  Per MFMA step
+// lane q holds A[i = q%16][k = q/16] = V and B[k = q/16][j = q%16] = X;
+// the 16x16 result sits in 4 doubles per lane: row 4*(q/16)+r, column q%16.
+template <class S, int MT, int NT>
+__global__ __launch_bounds__(256) void k_proj_dot_mfma(const double2 *__restrict__ V, int l, long vstride,
+                                                       const S *__restrict__ X, long xstride,
+                                                       const int *slots, int n, int Vp, int g5x, long chunk,
+                                                       double2 *__restrict__ part)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = lane & 15, kq = lane >> 4;
+    const long K = 12L * Vp, half = 6L * Vp;
+    const long k0 = (long)blockIdx.x * chunk;
+    const long k1 = (k0 + chunk < K) ? k0 + chunk : K;
+
+    v4d cre[MT][NT], cim[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            cre[m][t] = (v4d){0, 0, 0, 0};
+            cim[m][t] = (v4d){0, 0, 0, 0};
+        }
+
+    // per-lane row pointers
+    const double2 *vp[MT];
+    bool vok[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const int i = (wave + 4 * m) * 16 + row;
+        vok[m] = i < l;
+        vp[m] = V + (long)(vok[m] ? i : 0) * vstride;
+    }
+    const S *xp[NT];
+    bool xok[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int j = t * 16 + row;
+        xok[t] = j < n;
+        const int s = xok[t] ? (slots ? slots[j] : j) : 0;
+        xp[t] = X + (long)s * xstride;
+    }
+
+    for (long kb = k0; kb < k1; kb += 4) {
+        const long k = kb + kq;
+        const bool kin = k < k1;
+        double xr[NT], xi[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            cx<double> x = (kin && xok[t]) ? ldc<double>(xp[t], k) : cx<double>{0.0, 0.0};
+            if (g5x && k >= half) x = {-x.x, -x.y};
+            xr[t] = x.x;
+            xi[t] = x.y;
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            double2 v = (kin && vok[m]) ? vp[m][k] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                // Re: vr xr + vi xi ; Im: vr xi - vi xr
+                cre[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, xr[t], cre[m][t], 0, 0, 0);
+                cre[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.y, xi[t], cre[m][t], 0, 0, 0);
+                cim[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, xi[t], cim[m][t], 0, 0, 0);
+                cim[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-v.y, xr[t], cim[m][t], 0, 0, 0);
+            }
+        }
+    }
+
+    // partial[chunk][j][i]
+    double2 *pc = part + (long)blockIdx.x * n * l;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = (wave + 4 * m) * 16 + 4 * kq + r;
+                const int j = t * 16 + row;
+                if (i < l && j < n) pc[(long)j * l + i] = make_double2(cre[m][t][r], cim[m][t][r]);
+            }
+}
+
+// C[j][i] = sum_c part[c][j][i]  (fixed order)
+__global__ void k_proj_reduce(const double2 *__restrict__ part, int nchunk, int nl, double2 *__restrict__ C)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nl) return;
+    double r = 0, im = 0;
+    for (int c = 0; c < nchunk; ++c) {
+        double2 v = part[(long)c * nl + e];
+        r += v.x;
+        im += v.y;
+    }
+    C[e] = make_double2(r, im);
+}
+
+// --------------------------------------------------------------- X + V E (MFMA)
+// Y = alpha X + beta (V E).  Output tile D[j][k] (16 RHS x 16 consecutive k) += A[j][i] B[i][k] with
+// A = E (transposed coefficients) and B = V; lane q holds A[j = q%16][i = q/16]
+// and B[i = q/16][k = q%16]; the result row j = 4*(q/16)+r, column k = q%16,
+// so a store instruction writes four runs of 16 consecutive k.
+// Each wave owns 16 consecutive k (one column block) and NT RHS tiles.
+template <class SX, class SY, int NT>
+__global__ __launch_bounds__(256) void k_proj_expand_mfma(const double2 *__restrict__ V, int l, long vstride,
+                                                          const SX *X, long xstride, double alpha,
+                                                          SY *Y, long ystride, const int *slots, int n,
+                                                          int Vp, const double2 *__restrict__ E, double beta)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, iq = lane >> 4;
+    const long K = 12L * Vp;
+    const long kbase = ((long)blockIdx.x * 4 + wave) * 16;
+    if (kbase >= K) return;
+    const long kk = kbase + col;          // B column handled by this lane
+    const bool kok = kk < K;
+
+    v4d dre[NT], dim[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        dre[t] = (v4d){0, 0, 0, 0};
+        dim[t] = (v4d){0, 0, 0, 0};
+    }
+    for (int ib = 0; ib < l; ib += 4) {
+        const int i = ib + iq;
+        double2 v = (i < l && kok) ? V[(long)i * vstride + kk] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int j = t * 16 + col;    // A row held by this lane: j = q%16, i = q/16
+            double2 e = (i < l && j < n) ? E[(long)j * l + i] : make_double2(0.0, 0.0);
+            // (e * v): Re = er vr - ei vi ; Im = er vi + ei vr
+            dre[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.x, v.x, dre[t], 0, 0, 0);
+            dre[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-e.y, v.y, dre[t], 0, 0, 0);
+            dim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.x, v.y, dim[t], 0, 0, 0);
+            dim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.y, v.x, dim[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = t * 16 + 4 * iq + r;
+            if (j < n && kok) {
+                const int s = slots ? slots[j] : j;
+                cx<double> y = {beta * dre[t][r], beta * dim[t][r]};
+                if (X) {
+                    cx<double> x = ldc<double>(X + (long)s * xstride, kk);
+                    y.x = fma(alpha, x.x, y.x);
+                    y.y = fma(alpha, x.y, y.y);
+                }
+                stc<double>(Y + (long)s * ystride, kk, y);
+            }
+        }
+}
+
+// E[j][i] = sgn(lambda_i) C[j][i] - D[j][i]
+__global__ void k_small_combine(const double2 *C, const double2 *D, const double *sgn, int l, int n,
+                                double2 *E)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= l * n) return;
+    const int i = e % l;
+    const double s = sgn[i];
+    E[e] = make_double2(s * C[e].x - D[e].x, s * C[e].y - D[e].y);
+}
+
+// E[j][i] = C[j][i] * w[j][i]  (real weights, e.g. inverse Galerkin diagonal)
+__global__ void k_mul_coef(const double2 *C, const double *w, int l, int n, double2 *E)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= l * n) return;
+    E[e] = make_double2(C[e].x * w[e], C[e].y * w[e]);
+}
+
+// ------------------------------------------------------------------ launchers
+long proj_dot_chunk(long K)
+{
+    // split K so that about 1024 workgroups run (4 per CU); each chunk a multiple of 4
+    long c = (K + 1023) / 1024;
+    c = (c + 3) & ~3L;
+    if (c < 64) c = 64;
+    return c;
+}
+
+template <class S, int MT, int NT>
+static void launch_dot_mt(const double2 *V, int l, long vstride, const S *X, long xstride, const int *slots,
+                          int n, int Vp, int g5x, long chunk, int nchunk, double2 *part, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_proj_dot_mfma<S, MT, NT>), dim3(nchunk), dim3(256), 0, st, V, l, vstride, X, xstride,
+                       slots, n, Vp, g5x, chunk, part);
+}
+
+template <class S>
+hipError_t launch_proj_dot(const double2 *V, int l, long vstride, const S *X, long xstride, const int *slots,
+                           int n, int Vp, int g5x, double2 *part, double2 *C, hipStream_t st)
+{
+    if (l <= 0 || n <= 0) return hipSuccess;
+    if (n > 48 || l > 256) return hipErrorInvalidValue;   // caller splits larger batches
+    const long K = 12L * Vp;
+    const long chunk = proj_dot_chunk(K);
+    const int nchunk = (int)((K + chunk - 1) / chunk);
+    const int mt = ((l + 15) / 16 + 3) / 4;   // vector tiles per wave
+    const int nt = (n + 15) / 16;
+#define OV_DOT_CASE(M, N) \
+    if (mt == M && nt == N) launch_dot_mt<S, M, N>(V, l, vstride, X, xstride, slots, n, Vp, g5x, chunk, nchunk, part, st)
+    OV_DOT_CASE(1, 1); else OV_DOT_CASE(1, 2); else OV_DOT_CASE(1, 3);
+    else OV_DOT_CASE(2, 1); else OV_DOT_CASE(2, 2); else OV_DOT_CASE(2, 3);
+    else OV_DOT_CASE(3, 1); else OV_DOT_CASE(3, 2); else OV_DOT_CASE(3, 3);
+    else OV_DOT_CASE(4, 1); else OV_DOT_CASE(4, 2); else OV_DOT_CASE(4, 3);
+    else return hipErrorInvalidValue;
+#undef OV_DOT_CASE
+    const int nl = n * l;
+    hipLaunchKernelGGL(k_proj_reduce, dim3((nl + 255) / 256), dim3(256), 0, st, part, nchunk, nl, C);
+    return hipGetLastError();
+}
+
+template <class SX, class SY>
+hipError_t launch_proj_expand(const double2 *V, int l, long vstride, const SX *X, long xstride, double alpha,
+                              SY *Y, long ystride, const int *slots, int n, int Vp, const double2 *E, double beta,
+                              hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (n > 48) return hipErrorInvalidValue;
+    const long K = 12L * Vp;
+    const int nblk = (int)((K + 63) / 64);
+    const int nt = (n + 15) / 16;
+    if (nt == 1)
+        hipLaunchKernelGGL((k_proj_expand_mfma<SX, SY, 1>), dim3(nblk), dim3(256), 0, st, V, l, vstride, X, xstride,
+                           alpha, Y, ystride, slots, n, Vp, E, beta);
+    else if (nt == 2)
+        hipLaunchKernelGGL((k_proj_expand_mfma<SX, SY, 2>), dim3(nblk), dim3(256), 0, st, V, l, vstride, X, xstride,
+                           alpha, Y, ystride, slots, n, Vp, E, beta);
+    else
+        hipLaunchKernelGGL((k_proj_expand_mfma<SX, SY, 3>), dim3(nblk), dim3(256), 0, st, V, l, vstride, X, xstride,
+                           alpha, Y, ystride, slots, n, Vp, E, beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_combine(const double2 *C, const double2 *D, const double *sgn, int l, int n, double2 *E,
+                                hipStream_t st)
+{
+    if (l * n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_small_combine, dim3((l * n + 255) / 256), dim3(256), 0, st, C, D, sgn, l, n, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_mul_coef(const double2 *C, const double *w, int l, int n, double2 *E, hipStream_t st)
+{
+    if (l * n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mul_coef, dim3((l * n + 255) / 256), dim3(256), 0, st, C, w, l, n, E);
+    return hipGetLastError();
+}
+
+#define OV_INST_DOT(S)                                                                                       \
+    template hipError_t launch_proj_dot<S>(const double2 *, int, long, const S *, long, const int *, int, int, \
+                                           int, double2 *, double2 *, hipStream_t);
+OV_INST_DOT(double2)
+OV_INST_DOT(float2)
+OV_INST_DOT(uint32_t)
+#define OV_INST_EXP(A, B)                                                                                       \
+    template hipError_t launch_proj_expand<A, B>(const double2 *, int, long, const A *, long, double, B *, long, \
+                                                 const int *, int, int, const double2 *, double, hipStream_t);
+OV_INST_EXP(double2, double2)
+OV_INST_EXP(float2, float2)
+OV_INST_EXP(uint32_t, uint32_t)
+OV_INST_EXP(float2, double2)
+OV_INST_EXP(double2, float2)
+OV_INST_EXP(uint32_t, double2)
+OV_INST_EXP(double2, uint32_t)
+
+}  // namespace ov

@@ -1,0 +1,259 @@
+"""Thin ctypes binding of ``libov.so`` (the C ABI declared in include/ov.h).
+
+Argument marshalling only: every operation runs in the HIP library.  Torch
+supplies device memory (complex128 CUDA tensors in the canonical layouts) and
+the stream.  If ``libov.so`` is missing this module raises at import time;
+there is no fallback path.
+
+Two layers:
+
+* ``lib`` -- the raw ``ov_*`` functions with ctypes signatures;
+* ``Context`` -- one lattice context, methods named like the C entry points
+  without the ``ov_`` prefix (``ctx.dslash``, ``ctx.sign_apply``,
+  ``ctx.dov_apply``, ``ctx.deflated_cg``, ``ctx.sign_backward`` ...).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libov.so")
+
+OV_OK, OV_EINVAL, OV_ENOMEM, OV_EHIP, OV_ENOCONV, OV_ENAN, OV_ESTATE, OV_ENORM = 0, -1, -2, -3, -4, -5, -6, -7
+OV_FP64, OV_FP32, OV_BF16 = 0, 1, 2
+OV_PERIODIC, OV_ANTIPERIODIC, OV_DIRICHLET = 0, 1, 2
+OV_OP_DW, OV_OP_HW = 0, 1
+PREC = {"fp64": OV_FP64, "fp32": OV_FP32, "bf16": OV_BF16}
+STATUS = {0: "OV_OK", -1: "OV_EINVAL", -2: "OV_ENOMEM", -3: "OV_EHIP", -4: "OV_ENOCONV",
+          -5: "OV_ENAN", -6: "OV_ESTATE", -7: "OV_ENORM"}
+
+
+class OvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CgOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("inner_prec", C.c_int),
+                ("inner_tol", C.c_double), ("max_restarts", C.c_int), ("use_deflation", C.c_int)]
+
+
+class CgReport(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("relres", C.c_double), ("status", C.c_int)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libov.so not found at {LIB_PATH}; build it with "
+                          "`python -m paper_1111_6288_amd.build` (needs hipcc)")
+    L = C.CDLL(LIB_PATH)
+    vp, i, d, cp = C.c_void_p, C.c_int, C.c_double, C.POINTER
+    sig = {
+        "ov_create": ([cp(C.c_int32), cp(C.c_int32), d, i, cp(vp)], i),
+        "ov_destroy": ([vp], i),
+        "ov_set_stream": ([vp, vp], i),
+        "ov_last_error": ([vp], C.c_char_p),
+        "ov_upload_gauge": ([vp, vp], i),
+        "ov_set_fields": ([vp, i, cp(d), cp(d)], i),
+        "ov_set_sign_params": ([vp, i, d, d, cp(d)], i),
+        "ov_upload_eigvecs": ([vp, i, i, vp, cp(d)], i),
+        "ov_upload_deflation": ([vp, i, i, vp], i),
+        "ov_dslash": ([vp, i, i, i, cp(i), vp, vp], i),
+        "ov_sign_apply": ([vp, i, i, cp(i), vp, vp], i),
+        "ov_dov_apply": ([vp, i, i, cp(i), cp(d), i, vp, vp], i),
+        "ov_deflated_cg": ([vp, i, cp(i), cp(d), vp, vp, cp(CgOpts), cp(CgReport)], i),
+        "ov_sign_backward": ([vp, i, vp, vp, vp, cp(d), vp, i], i),
+        "ov_prof_enable": ([vp, i], i),
+        "ov_prof_query": ([vp, C.c_char_p, cp(C.c_long), cp(d), cp(d)], i),
+        "ov_set_tuning": ([vp, i, i, i], i),
+        "ov_get_tuning": ([vp, i, cp(i), cp(i)], i),
+        "ov_autotune": ([vp, i, i, C.c_char_p], i),
+        "ov_memory_used": ([vp, cp(C.c_int64)], i),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+lib = _load()
+EXPORTED = ("ov_create", "ov_destroy", "ov_set_stream", "ov_last_error", "ov_upload_gauge", "ov_set_fields",
+            "ov_set_sign_params", "ov_upload_eigvecs", "ov_upload_deflation", "ov_dslash", "ov_sign_apply",
+            "ov_dov_apply", "ov_deflated_cg", "ov_sign_backward", "ov_prof_enable", "ov_prof_query",
+            "ov_set_tuning", "ov_get_tuning", "ov_autotune", "ov_memory_used")
+
+
+def _ints(v):
+    v = [int(a) for a in v]
+    return (C.c_int * len(v))(*v)
+
+
+def _doubles(v):
+    v = [float(a) for a in v]
+    return (C.c_double * len(v))(*v)
+
+
+def _dev(t, shape_tail, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{name} must be complex128 (canonical layout)")
+    if tuple(t.shape[-len(shape_tail):]) != tuple(shape_tail):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected (..., {shape_tail})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One lattice on one GPU: links, background fields, sign parameters, small spaces."""
+
+    def __init__(self, L, bc, mw, device=0, stream=None):
+        self.L = tuple(int(v) for v in L)
+        self.V = self.L[0] * self.L[1] * self.L[2] * self.L[3]
+        self.device = int(device)
+        h = C.c_void_p()
+        rc = lib.ov_create((C.c_int32 * 4)(*self.L), (C.c_int32 * 4)(*[int(b) for b in bc]), float(mw),
+                           self.device, C.byref(h))
+        if rc != OV_OK or not h.value:
+            raise OvError(rc, f"ov_create failed for L={self.L}, bc={tuple(bc)}")
+        self._h = h
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.set_stream(stream)
+
+    # ------------------------------------------------------------ plumbing
+    def _chk(self, rc):
+        if rc != OV_OK:
+            raise OvError(rc, lib.ov_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            lib.ov_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self.stream = stream
+        return self._chk(lib.ov_set_stream(self._h, C.c_void_p(stream.cuda_stream)))
+
+    def memory_used(self):
+        b = C.c_int64()
+        self._chk(lib.ov_memory_used(self._h, C.byref(b)))
+        return b.value
+
+    # ------------------------------------------------------------ setup
+    def upload_gauge(self, U):
+        return self._chk(lib.ov_upload_gauge(self._h, _dev(U, (4, self.V, 3, 3), "U")))
+
+    def set_fields(self, q, eta):
+        q, eta = list(q), list(eta)
+        return self._chk(lib.ov_set_fields(self._h, len(q), _doubles(q), _doubles(eta)))
+
+    def set_sign_params(self, n, eps, norm=0.0, coeffs=None):
+        cp = _doubles(coeffs) if coeffs is not None else None
+        return self._chk(lib.ov_set_sign_params(self._h, int(n), float(eps), float(norm), cp))
+
+    def upload_eigvecs(self, field, V, lam):
+        l = 0 if V is None else int(V.shape[0])
+        ptr = _dev(V, (self.V, 4, 3), "V") if l else None
+        return self._chk(lib.ov_upload_eigvecs(self._h, int(field), l, ptr, _doubles(lam) if l else None))
+
+    def upload_deflation(self, field, W):
+        k = 0 if W is None else int(W.shape[0])
+        ptr = _dev(W, (self.V, 4, 3), "W") if k else None
+        return self._chk(lib.ov_upload_deflation(self._h, int(field), k, ptr))
+
+    # ------------------------------------------------------------ operators
+    def _io(self, x, fields):
+        if x.dim() == 3:
+            x = x.unsqueeze(0)
+        n = int(x.shape[0])
+        fields = [0] * n if fields is None else list(fields)
+        if len(fields) != n:
+            raise ValueError("fields must have one entry per RHS")
+        return x, n, fields
+
+    def dslash(self, x, fields=None, op="HW", prec="fp64"):
+        x, n, fields = self._io(x, fields)
+        y = torch.empty_like(x)
+        opc = OV_OP_HW if op == "HW" else OV_OP_DW
+        self._chk(lib.ov_dslash(self._h, PREC[prec], opc, n, _ints(fields), _dev(x, (self.V, 4, 3), "x"),
+                                _dev(y, (self.V, 4, 3), "y")))
+        return y
+
+    def sign_apply(self, x, fields=None, prec="fp64"):
+        x, n, fields = self._io(x, fields)
+        y = torch.empty_like(x)
+        self._chk(lib.ov_sign_apply(self._h, PREC[prec], n, _ints(fields), _dev(x, (self.V, 4, 3), "x"),
+                                    _dev(y, (self.V, 4, 3), "y")))
+        return y
+
+    def dov_apply(self, x, fields=None, mass=None, dagger=False, prec="fp64", out=None):
+        x, n, fields = self._io(x, fields)
+        mass = [0.0] * n if mass is None else list(mass)
+        y = torch.empty_like(x) if out is None else out
+        self._chk(lib.ov_dov_apply(self._h, PREC[prec], n, _ints(fields), _doubles(mass), int(bool(dagger)),
+                                   _dev(x, (self.V, 4, 3), "x"), _dev(y, (self.V, 4, 3), "y")))
+        return y
+
+    def deflated_cg(self, b, fields=None, mass=None, x0=None, tol=1e-10, maxiter=10000, inner_prec="fp32",
+                    inner_tol=1e-5, max_restarts=50, use_deflation=True, raise_on_noconv=True):
+        b, n, fields = self._io(b, fields)
+        mass = [0.0] * n if mass is None else list(mass)
+        x = torch.zeros_like(b) if x0 is None else x0.clone().reshape(b.shape).contiguous()
+        opts = CgOpts(float(tol), int(maxiter), PREC[inner_prec], float(inner_tol), int(max_restarts),
+                      int(bool(use_deflation)))
+        rep = (CgReport * n)()
+        rc = lib.ov_deflated_cg(self._h, n, _ints(fields), _doubles(mass), _dev(b, (self.V, 4, 3), "b"),
+                                _dev(x, (self.V, 4, 3), "x"), C.byref(opts), rep)
+        report = [dict(iters=r.iters, restarts=r.restarts, relres=r.relres, status=r.status) for r in rep]
+        if rc != OV_OK and not (rc == OV_ENOCONV and not raise_on_noconv):
+            self._chk(rc)
+        return x, report
+
+    def sign_backward(self, field, x, g, want_U=True, want_eta=True, want_x=True, ckpt_every=32):
+        x = x.reshape(self.V, 4, 3).contiguous()
+        g = g.reshape(self.V, 4, 3).contiguous()
+        gU = torch.empty((4, self.V, 3, 3), dtype=torch.complex128, device=x.device) if want_U else None
+        gx = torch.empty_like(x) if want_x else None
+        ge = C.c_double(0.0)
+        self._chk(lib.ov_sign_backward(self._h, int(field), _dev(x, (self.V, 4, 3), "x"),
+                                       _dev(g, (self.V, 4, 3), "g"),
+                                       _dev(gU, (4, self.V, 3, 3), "gU") if want_U else None,
+                                       C.byref(ge) if want_eta else None,
+                                       _dev(gx, (self.V, 4, 3), "gx") if want_x else None, int(ckpt_every)))
+        return gU, (ge.value if want_eta else None), gx
+
+    # ------------------------------------------------------------ measurement and tuning
+    def prof_enable(self, on=True):
+        return self._chk(lib.ov_prof_enable(self._h, int(bool(on))))
+
+    def prof_query(self, cls):
+        n, ms, by = C.c_long(), C.c_double(), C.c_double()
+        self._chk(lib.ov_prof_query(self._h, cls.encode(), C.byref(n), C.byref(ms), C.byref(by)))
+        return n.value, ms.value, by.value
+
+    def set_tuning(self, prec, rhs_per_thread, block):
+        return self._chk(lib.ov_set_tuning(self._h, PREC[prec], int(rhs_per_thread), int(block)))
+
+    def get_tuning(self, prec):
+        a, b = C.c_int(), C.c_int()
+        self._chk(lib.ov_get_tuning(self._h, PREC[prec], C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def autotune(self, prec, nrhs, cache_path=None):
+        return self._chk(lib.ov_autotune(self._h, PREC[prec], int(nrhs),
+                                         cache_path.encode() if cache_path else None))
