@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Throughput of the overlap operator on one MI355X: D_ov applies per second.
+
+Workload (24^3 x 48, the batched multi-RHS configuration): Dirichlet
+boundaries in x and t, periodic in y and z; SU(3) links exp(i 0.2 H);
+Wilson mass -1.5; sign(H_w) by an order-300 Chebyshev polynomial on
+[1.234e-3, 1] (delta ~ 1e-10 by eq. (2)) with a 200-vector small space per
+background field; 108 right-hand sides = 12 spin-colour point sources x
+3 field strengths (q = 2/3, eta in {0, +1e-3, -1e-3}) x 3 quark masses
+{0.01, 0.02, 0.05}.
+
+One step = one D(m) application (alternately D and D^dag) to all 108 RHS in
+the mixed path: FP32 Wilson dslash and Clenshaw recursion, FP64 small-space
+projection.  value = 108 * steps / seconds.  The same batch is then run on
+the FP64 path for the speedup at matched work, and the mixed result is
+compared with the FP64 one per RHS.  The dominant kernel (dslash with the
+fused Clenshaw epilogue) is timed live with HIP events on the library's
+stream during the timed steps, for the roofline figure.
+
+Small spaces are seeded random orthonormal bases (the eigensolver that would
+produce real ones is not part of this path); they cost the same as
+eigenvectors.  All data are synthetic.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+L = (24, 24, 24, 48)
+BC = (2, 0, 0, 2)
+MW = -1.5
+NPOLY = 300
+EPS = 1.234e-3
+NORM = 6.5
+LSMALL = 200
+Q = 2.0 / 3.0
+ETAS = (0.0, 1e-3, -1e-3)
+MASSES = (0.01, 0.02, 0.05)
+SRC = (12, 0, 0, 24)
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=4)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--fp64-steps", type=int, default=2)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-fp64", action="store_true")
+    p.add_argument("--lsmall", type=int, default=LSMALL)
+    p.add_argument("--npoly", type=int, default=NPOLY)
+    return p.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("dslash.hip", "spin.h", "ov_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_1111_6288_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(prec, nrhs):
+    """HBM bytes per launch of the Clenshaw kernel from committed rocprofv3 PMC runs, if current."""
+    path = os.path.join(ROOT, "profiles", "clenshaw_dslash_24x48_108rhs_pmc.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("prec") != prec or rec.get("nrhs") != nrhs:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def build_inputs(torch, ov, args):
+    import synth
+
+    V = synth.volume(L)
+    t0 = time.time()
+    U = synth.su3_links(L, 0.2, 2022)
+    ctx = ov.Context(L, BC, MW, device=0)
+    ctx.upload_gauge(torch.from_numpy(U).cuda())
+    ctx.set_fields([Q] * len(ETAS), list(ETAS))
+    ctx.set_sign_params(args.npoly, EPS, NORM)
+    for f in range(len(ETAS)):
+        Vs = synth.random_orthonormal_torch(L, args.lsmall, 500 + f, "cuda")
+        lam = [(-1.0) ** i * (0.05 + 0.001 * i) for i in range(args.lsmall)]
+        ctx.upload_eigvecs(f, Vs, lam)
+        del Vs
+        torch.cuda.empty_cache()
+    fields, masses, idx = [], [], []
+    for f in range(len(ETAS)):
+        for m in MASSES:
+            for s in range(12):
+                fields.append(f)
+                masses.append(m)
+                idx.append(s)
+    n = len(fields)
+    x = torch.zeros((n, V, 4, 3), dtype=torch.complex128, device="cuda")
+    site = synth.site_index(L, *SRC)
+    for j, s in enumerate(idx):
+        x[j, site, s // 3, s % 3] = 1.0
+    torch.cuda.synchronize()
+    return ctx, U, x, fields, masses, time.time() - t0
+
+
+def timed_applies(torch, ctx, x, y, fields, masses, prec, steps, warmup, prof):
+    for w in range(warmup):
+        ctx.dov_apply(x, fields, masses, dagger=bool(w % 2), prec=prec, out=y)
+    torch.cuda.synchronize()
+    if prof:
+        ctx.prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ctx.dov_apply(x, fields, masses, dagger=bool(k % 2), prec=prec, out=y)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = {}
+    if prof:
+        for cls in ("clenshaw", "dslash", "proj_dot", "proj_expand", "blas"):
+            stats[cls] = ctx.prof_query(cls)
+        ctx.prof_enable(False)
+    return dt, stats
+
+
+def cpu_baseline():
+    """Bounded sample of the FP64 oracle on the host: D(m) on one RHS at 24^3 x 48.
+
+    Runs the oracle's D(m) with (n, l) = (2, 0), (6, 0) and (2, 8), fits
+    time = a + b n + c l, and reports 1 / (a + 300 b + 200 c) applies/s.
+    """
+    import numpy as np
+
+    import synth
+    from oracle import api
+
+    U = synth.su3_links(L, 0.2, 2022)
+    lat = api.Lattice(L, BC, MW, U, Q * ETAS[1])
+    x = synth.point_sources(L, SRC)[0]
+    Vs = synth.random_orthonormal(L, 8, 9)
+    lam = np.linspace(-1, 1, 8)
+
+    def run(n, l):
+        sp = api.SignParams(n, EPS, NORM, Vs[:l] if l else None, lam[:l] if l else None)
+        t0 = time.perf_counter()
+        api.dov(lat, sp, x, MASSES[1])
+        return time.perf_counter() - t0
+
+    run(1, 0)
+    t20, t60, t28 = run(2, 0), run(6, 0), run(2, 8)
+    b = (t60 - t20) / 4.0
+    a = t20 - 2 * b
+    cvec = max(t28 - t20, 0.0) / 8.0
+    t_apply = a + NPOLY * b + LSMALL * cvec
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": 1.0 / t_apply, "unit": "D_ov applies/s", "cores": cores, "kind": "oracle",
+        "sample": (f"FP64 oracle D(m) on 1 point source at 24^3x48, timed at (n,l)=(2,0),(6,0),(2,8) "
+                   f"[{t20:.2f}s, {t60:.2f}s, {t28:.2f}s], scaled linearly to n=300, l=200: "
+                   f"{t_apply:.1f} s per apply"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "gpus_requested": args.gpus}), flush=True)
+        sys.exit(2)
+    import torch
+    from paper_1111_6288_amd import ov
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(1)
+
+    print(f"[bench] building inputs: L={L}, n={args.npoly}, l={args.lsmall}", file=sys.stderr, flush=True)
+    ctx, U, x, fields, masses, t_setup = build_inputs(torch, ov, args)
+    nrhs = len(fields)
+    ctx.autotune("fp32", nrhs)
+    tuned = ctx.get_tuning("fp32")
+    print(f"[bench] setup {t_setup:.1f}s, fp32 tuning {tuned}", file=sys.stderr, flush=True)
+
+    y32 = torch.empty_like(x)
+    dt, stats = timed_applies(torch, ctx, x, y32, fields, masses, "fp32", args.steps, args.warmup, True)
+    applies = nrhs * args.steps
+    value = applies / dt
+    print(f"[bench] mixed: {args.steps} steps in {dt:.2f}s -> {value:.2f} applies/s", file=sys.stderr, flush=True)
+
+    # last step applied D^dag when steps is even, D otherwise; recompute D on a fixed slice for the error check
+    ctx.dov_apply(x, fields, masses, dagger=False, prec="fp32", out=y32)
+    fp64 = None
+    err = None
+    if not args.no_fp64:
+        y64 = torch.empty_like(x)
+        dt64, _ = timed_applies(torch, ctx, x, y64, fields, masses, "fp64", args.fp64_steps, 1, False)
+        fp64 = nrhs * args.fp64_steps / dt64
+        ctx.dov_apply(x, fields, masses, dagger=False, prec="fp64", out=y64)
+        d = (y32 - y64).reshape(nrhs, -1).norm(dim=1) / y64.reshape(nrhs, -1).norm(dim=1)
+        err = float(d.max())
+        del y64
+        print(f"[bench] fp64: {fp64:.2f} applies/s; mixed vs fp64 max rel err {err:.2e}", file=sys.stderr,
+              flush=True)
+
+    n_launch, ms, by = stats["clenshaw"]
+    avg_ms = ms / max(n_launch, 1)
+    bytes_per_launch = by / max(n_launch, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic("fp32", nrhs),
+                "kernel": "k_dslash<float2,NR,HW,EPI> (dslash + fused Clenshaw epilogue)",
+                "launches": n_launch, "avg_ms": round(avg_ms, 4),
+                "algorithmic_bytes_per_launch": bytes_per_launch}
+    kernels = {k: {"launches": v[0], "ms": round(v[1], 2), "GBps": round(v[2] / max(v[1], 1e-9) / 1e6, 1)}
+               for k, v in stats.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle on host cores)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+
+    line = {
+        "metric": "D_ov applies/s at 24^3x48 (dslash HBM GB/s), mixed+multiRHS vs FP64 at 1e-10",
+        "value": round(value, 3), "unit": "D_ov applies/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "24^3x48 overlap D(m) apply, 108 RHS (12 point sources x 3 eta x 3 masses), "
+                               "order-300 Chebyshev sign, 200-vector small space per field, mixed FP32/FP64",
+                   "lattice": list(L), "nrhs": nrhs, "npoly": args.npoly, "lsmall": args.lsmall,
+                   "bc": "Dirichlet x,t; periodic y,z", "projection_dtype": "f64",
+                   "tuning_fp32": {"rhs_per_thread": tuned[0], "block": tuned[1]}},
+        "fp64_applies_per_s": None if fp64 is None else round(fp64, 3),
+        "speedup_vs_fp64": None if fp64 is None else round(value / fp64, 3),
+        "mixed_vs_fp64_max_rel_err": err,
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

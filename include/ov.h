@@ -100,6 +100,13 @@ int ov_upload_gauge(ov_ctx *ctx, const void *U_dev);
 int ov_set_fields(ov_ctx *ctx, int nfield, const double *q, const double *eta);
 
 /*
+ * Change the charge and field strength of one existing group (Sec. 4,
+ * eq. (3)) without touching its small space or deflation basis; used when
+ * those are held fixed while eta varies (adjoint, finite differences).
+ */
+int ov_set_field_eta(ov_ctx *ctx, int field, double q, double eta);
+
+/*
  * Polynomial parameters of sign(H_w) ~ Q P(Q^2), Q = H_w / norm (Sec. 2):
  * degree n >= 1 in Q^2, interval [eps, 1] for Q^2 (0 < eps < 1), and
  * norm >= ||H_w|| (the default bound |4+m_w| + 4 is valid for any links;
@@ -217,6 +224,15 @@ int ov_prof_query(ov_ctx *ctx, const char *kernel_class, long *launches, double 
 int ov_set_tuning(ov_ctx *ctx, int prec, int rhs_per_thread, int block);
 int ov_get_tuning(ov_ctx *ctx, int prec, int *rhs_per_thread, int *block);
 int ov_autotune(ov_ctx *ctx, int prec, int nrhs, const char *cache_path);
+
+/*
+ * Capture of the sign / D(m) pipelines in HIP graphs (default on): the first
+ * call with a given batch signature runs eagerly, the second captures the
+ * launch sequence, later identical calls replay it.  Any change of links
+ * packing, fields, small spaces, polynomial, tuning or workspace size drops
+ * the captured graphs.  on = 0 runs every launch eagerly.
+ */
+int ov_set_graphs(ov_ctx *ctx, int on);
 
 /* Bytes of device memory the context holds right now. */
 int ov_memory_used(const ov_ctx *ctx, int64_t *bytes);

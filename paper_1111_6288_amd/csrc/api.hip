@@ -102,6 +102,11 @@ struct ov_ctx {
     int *d_count = nullptr;
 
     size_t mem_bytes = 0;
+
+    // captured pipelines (hipGraph), keyed by everything the launch sequence depends on
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    std::map<std::string, std::pair<int, hipGraphExec_t>> graphs;   // (times seen, executable)
 };
 
 namespace {
@@ -158,12 +163,22 @@ size_t field_bytes(const ov_ctx *c) { return field_elems(c) * sizeof(S); }
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Drop every captured pipeline: called whenever a pointer or a constant that
+// a capture baked in changes (arena, phase table, small spaces, polynomial, tuning).
+void invalidate_graphs(ov_ctx *c)
+{
+    for (auto &kv : c->graphs)
+        if (kv.second.second) (void)hipGraphExecDestroy(kv.second.second);
+    c->graphs.clear();
+}
+
 // Make sure the arena holds `bytes`; only called before any pointer is handed out.
 int ws_reserve(ov_ctx *c, size_t bytes)
 {
     c->ws_top = 0;
     if (bytes <= c->ws_size) return OV_OK;
     HIPCHK(hipStreamSynchronize(c->stream));
+    invalidate_graphs(c);
     dev_free(c, c->ws, c->ws_size);
     c->ws = nullptr;
     c->ws_size = 0;
@@ -190,6 +205,53 @@ hipError_t h2d(ov_ctx *c, void *dst, const void *src, size_t bytes)
     hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(c->stream);
+}
+
+// Run `body` (a sequence of kernel launches on c->stream, no host sync, no
+// allocation, no memset) through a cached hipGraph: the first call with a
+// key runs eagerly (this fills every cache the body needs), the second one
+// captures on a private stream and launches the graph on c->stream, later
+// ones replay it.  Profiling turns capture off.
+template <class F>
+int run_graph(ov_ctx *c, const std::string &key, F &&body)
+{
+    if (!c->use_graphs || c->prof_on) return body();
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        c->graphs[key] = {1, nullptr};
+        return body();
+    }
+    if (it->second.second) {
+        HIPCHK(hipGraphLaunch(it->second.second, c->stream));
+        return OV_OK;
+    }
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t saved = c->stream;
+    c->stream = c->cap_stream;
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = body();
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    c->stream = saved;
+    if (rc != OV_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(c, OV_EHIP, "stream capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(c, OV_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    it->second.second = exec;
+    HIPCHK(hipGraphLaunch(exec, c->stream));
+    return OV_OK;
+}
+
+template <class T>
+void key_add(std::string &k, const std::vector<T> &v)
+{
+    k.append((const char *)v.data(), v.size() * sizeof(T));
+    k.push_back('|');
 }
 
 const int *dev_ints(ov_ctx *c, const std::vector<int> &v)
@@ -673,6 +735,7 @@ int upload_phase(ov_ctx *c)
             const double th = c->q[f] * c->eta[f] * t;
             h[(size_t)f * Lt + t] = {std::cos(th), std::sin(th)};
         }
+    invalidate_graphs(c);
     if (c->phase) dev_free(c, c->phase, 0);
     c->phase = nullptr;
     CHK(dev_alloc(c, (void **)&c->phase, h.size() * sizeof(cx<double>)));
@@ -720,7 +783,9 @@ int api_sign(ov_ctx *c, int nrhs, const std::vector<int> &grp, const void *x, vo
     const int *fg = dev_ints(c, grp);
     HIPCHK(launch_pack_spinor<S>((const double2 *)x, X, (long)field_elems(c), nullptr, nrhs, c->g.V, c->g.Vp,
                                  c->stream));
-    CHK(sign_batch<S>(c, b, fg, X, X, w));
+    std::string key = "sign|" + std::to_string(PrecOf<S>::p) + "|";
+    key_add(key, grp);
+    CHK(run_graph(c, key, [&]() { return sign_batch<S>(c, b, fg, X, X, w); }));
     HIPCHK(launch_unpack_spinor<S>(X, (double2 *)y, (long)field_elems(c), nullptr, nrhs, c->g.V, c->g.Vp,
                                    c->stream));
     return OV_OK;
@@ -741,7 +806,10 @@ int api_dov(ov_ctx *c, int nrhs, const std::vector<int> &grp, const double *mass
     CHK(mass_coefs(c, nrhs, mass, &ca, &cb));
     HIPCHK(launch_pack_spinor<S>((const double2 *)x, X, (long)field_elems(c), nullptr, nrhs, c->g.V, c->g.Vp,
                                  c->stream));
-    CHK(dov_batch<S>(c, b, fg, ca, cb, dagger != 0, X, X, w));
+    std::string key = "dov|" + std::to_string(PrecOf<S>::p) + "|" + std::to_string(dagger != 0) + "|";
+    key_add(key, grp);
+    key_add(key, std::vector<double>(mass, mass + nrhs));
+    CHK(run_graph(c, key, [&]() { return dov_batch<S>(c, b, fg, ca, cb, dagger != 0, X, X, w); }));
     HIPCHK(launch_unpack_spinor<S>(X, (double2 *)y, (long)field_elems(c), nullptr, nrhs, c->g.V, c->g.Vp,
                                    c->stream));
     return OV_OK;
@@ -812,6 +880,8 @@ int ov_destroy(ov_ctx *c)
     for (auto &kv : c->dcache) (void)hipFree(kv.second);
     for (auto &kv : c->ccache) (void)hipFree(kv.second);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    invalidate_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return OV_OK;
 }
@@ -874,6 +944,17 @@ int ov_set_fields(ov_ctx *c, int nfield, const double *q, const double *eta)
     return upload_phase(c);
 }
 
+int ov_set_field_eta(ov_ctx *c, int field, double q, double eta)
+{
+    CHK(check_ctx(c));
+    if (field < 0 || field >= c->nfield) return fail(c, OV_EINVAL, "field %d outside [0, %d)", field, c->nfield);
+    if (!std::isfinite(q) || !std::isfinite(eta)) return fail(c, OV_ENAN, "non-finite q or eta");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->q[field] = q;
+    c->eta[field] = eta;
+    return upload_phase(c);
+}
+
 int ov_set_sign_params(ov_ctx *c, int n, double eps, double norm, const double *coeffs)
 {
     CHK(check_ctx(c));
@@ -881,6 +962,7 @@ int ov_set_sign_params(ov_ctx *c, int n, double eps, double norm, const double *
     if (!(eps > 0 && eps < 1)) return fail(c, OV_EINVAL, "eps must lie in (0, 1)");
     if (norm <= 0) norm = std::fabs(4.0 + c->mw) + 4.0;
     if (!std::isfinite(norm)) return fail(c, OV_ENAN, "non-finite norm");
+    invalidate_graphs(c);
     c->npoly = n;
     c->eps = eps;
     c->norm = norm;
@@ -903,6 +985,7 @@ int ov_upload_eigvecs(ov_ctx *c, int field, int l, const void *V_dev, const doub
     if (l > 0 && (!V_dev || !lambda)) return fail(c, OV_EINVAL, "null V or lambda");
     Small &sm = c->small[field];
     HIPCHK(hipStreamSynchronize(c->stream));
+    invalidate_graphs(c);
     dev_free(c, sm.V, 16ul * 12 * c->g.Vp * sm.l);
     dev_free(c, sm.sgn, 8ul * sm.l);
     sm = Small();
@@ -996,6 +1079,15 @@ int ov_dov_apply(ov_ctx *c, int prec, int nrhs, const int *field_of_rhs, const d
     return api_dov<uint32_t>(c, nrhs, grp, mass, dagger, x, y);
 }
 
+int ov_set_graphs(ov_ctx *c, int on)
+{
+    CHK(check_ctx(c));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    invalidate_graphs(c);
+    c->use_graphs = on != 0;
+    return OV_OK;
+}
+
 int ov_prof_enable(ov_ctx *c, int on)
 {
     CHK(check_ctx(c));
@@ -1037,6 +1129,7 @@ int ov_set_tuning(ov_ctx *c, int prec, int rhs_per_thread, int block)
     if (rhs_per_thread != 1 && rhs_per_thread != 2 && rhs_per_thread != 4 && rhs_per_thread != 8)
         return fail(c, OV_EINVAL, "rhs_per_thread must be 1, 2, 4 or 8");
     if (block < 64 || block > 256 || block % 64) return fail(c, OV_EINVAL, "block must be 64, 128, 192 or 256");
+    invalidate_graphs(c);
     c->nr[prec] = rhs_per_thread;
     c->block[prec] = block;
     return OV_OK;
@@ -1522,6 +1615,7 @@ int ov_upload_deflation(ov_ctx *c, int field, int k, const void *W_dev)
     if (!c->have_gauge || !c->have_sign) return fail(c, OV_ESTATE, "upload the gauge field and set the sign first");
     Defl &d = c->defl[field];
     HIPCHK(hipStreamSynchronize(c->stream));
+    invalidate_graphs(c);
     dev_free(c, d.W, 16ul * 12 * c->g.Vp * d.k);
     d = Defl();
     if (k == 0) return OV_OK;
@@ -1636,6 +1730,7 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
             }
         }
         c->prof_on = was;
+        invalidate_graphs(c);
         c->nr[prec] = bnr;
         c->block[prec] = bbl;
         (void)hipEventDestroy(e0);

@@ -21,28 +21,45 @@
 
 namespace ov {
 
+// Loads address a plane through a wave-uniform base pointer plus a 32-bit
+// per-lane site offset, so that the compiler can use scalar-base addressing
+// instead of per-lane 64-bit address arithmetic.
 template <class S, class R>
-__device__ __forceinline__ void load_link(const S *__restrict__ U, int mu, int Vp, int s, cx<R> (&u)[3][3])
+__device__ __forceinline__ cx<R> ldp(const S *__restrict__ plane, unsigned site)
+{
+    const unsigned boff = site * (unsigned)sizeof(S);   // < 4 GiB: a plane holds at most 2^31/64 sites
+    return ldc<R>((const S *)((const char *)plane + boff), 0u);
+}
+
+template <class S, class R>
+__device__ __forceinline__ void stp(S *__restrict__ plane, unsigned site, cx<R> v)
+{
+    const unsigned boff = site * (unsigned)sizeof(S);
+    stc<R>((S *)((char *)plane + boff), 0u, v);
+}
+
+template <class S, class R>
+__device__ __forceinline__ void load_link(const S *__restrict__ U, int mu, int Vp, unsigned s, cx<R> (&u)[3][3])
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) u[a][b] = ldc<R>(U, (long)(mu * 9 + a * 3 + b) * Vp + s);
+        for (int b = 0; b < 3; ++b) u[a][b] = ldp<S, R>(U + (size_t)(mu * 9 + a * 3 + b) * (unsigned)Vp, s);
 }
 
 template <class S, class R>
-__device__ __forceinline__ void load_spinor(const S *__restrict__ x, int Vp, int s, cx<R> (&p)[4][3])
+__device__ __forceinline__ void load_spinor(const S *__restrict__ x, int Vp, unsigned s, cx<R> (&p)[4][3])
 {
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) p[sp][c] = ldc<R>(x, (long)(sp * 3 + c) * Vp + s);
+        for (int c = 0; c < 3; ++c) p[sp][c] = ldp<S, R>(x + (size_t)(sp * 3 + c) * (unsigned)Vp, s);
 }
 
 // One direction, both hops, for all NR right-hand sides of this thread.
 template <int MU, int NR, class S, class R>
 __device__ __forceinline__ void hop_dir(const DsArgs<S> &a, int site, int cmu, int Lmu, int stride,
-                                        const long (&off)[NR], const bool (&act)[NR],
+                                        const size_t (&off)[NR], const bool (&act)[NR],
                                         const cx<R> (&ph)[NR], cx<R> (&acc)[NR][4][3])
 {
     const int Vp = a.g.Vp;
@@ -53,12 +70,12 @@ __device__ __forceinline__ void hop_dir(const DsArgs<S> &a, int site, int cmu, i
         const R bf = wrap ? (R)a.g.bcf[MU] : (R)1;
         if (bf != (R)0) {
             cx<R> u[3][3];
-            load_link<S, R>(a.U, MU, Vp, site, u);
+            load_link<S, R>(a.U, MU, Vp, (unsigned)site, u);
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 if (!act[r]) continue;
                 cx<R> p[4][3], h[2][3], g[2][3];
-                load_spinor<S, R>(a.x + off[r], Vp, j, p);
+                load_spinor<S, R>(a.x + off[r], Vp, (unsigned)j, p);
                 project<MU, -1>(p, h);
                 if (MU == 0 || wrap) {
                     cx<R> f = (MU == 0) ? cscale(ph[r], bf) : cmk(bf, (R)0);
@@ -87,12 +104,12 @@ __device__ __forceinline__ void hop_dir(const DsArgs<S> &a, int site, int cmu, i
         const R bf = wrap ? (R)a.g.bcf[MU] : (R)1;
         if (bf != (R)0) {
             cx<R> u[3][3];
-            load_link<S, R>(a.U, MU, Vp, j, u);
+            load_link<S, R>(a.U, MU, Vp, (unsigned)j, u);
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 if (!act[r]) continue;
                 cx<R> p[4][3], h[2][3], g[2][3];
-                load_spinor<S, R>(a.x + off[r], Vp, j, p);
+                load_spinor<S, R>(a.x + off[r], Vp, (unsigned)j, p);
                 project<MU, +1>(p, h);
                 if (MU == 0 || wrap) {
                     cx<R> f = (MU == 0) ? cmk(ph[r].x * bf, -ph[r].y * bf) : cmk(bf, (R)0);
@@ -132,8 +149,32 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
     const Geo &g = a.g;
     const int blk = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
     const int site = blk * blockDim.x + threadIdx.x;
-    if (site >= g.V) return;
+    if (site >= g.Vp) return;
     const int j0 = blockIdx.y * NR;
+
+    size_t off[NR];
+    bool act[NR];
+    int grp[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int j = j0 + r;
+        act[r] = j < a.n;
+        const int jj = act[r] ? j : j0;
+        // the storage index depends on blockIdx.y only: make the compiler see it as uniform
+        const int s = __builtin_amdgcn_readfirstlane(a.slots ? a.slots[jj] : jj);
+        off[r] = (size_t)s * (size_t)a.fstride;
+        grp[r] = __builtin_amdgcn_readfirstlane(a.fgroup ? a.fgroup[s] : 0);
+    }
+    if (site >= g.V) {   // padding sites hold zeros in every field
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (!act[r]) continue;
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                stp<S, R>(a.y + off[r] + (size_t)k * (unsigned)g.Vp, (unsigned)site, cmk((R)0, (R)0));
+        }
+        return;
+    }
 
     int rem = site;
     const int xc = rem % g.Lx; rem /= g.Lx;
@@ -141,18 +182,10 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
     const int zc = rem % g.Lz;
     const int tc = rem / g.Lz;
 
-    long off[NR];
-    bool act[NR];
     cx<R> ph[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        const int j = j0 + r;
-        act[r] = j < a.n;
-        const int jj = act[r] ? j : j0;
-        const int s = a.slots ? a.slots[jj] : jj;
-        off[r] = (long)s * a.fstride;
-        const int grp = a.fgroup ? a.fgroup[s] : 0;
-        const cx<double> p = a.phase[grp * g.Lt + tc];
+        const cx<double> p = a.phase[grp[r] * g.Lt + tc];
         ph[r] = cmk((R)p.x, (R)p.y);
     }
 
@@ -175,7 +208,7 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
     for (int r = 0; r < NR; ++r) {
         if (!act[r]) continue;
         cx<R> p[4][3];
-        load_spinor<S, R>(a.x + off[r], g.Vp, site, p);
+        load_spinor<S, R>(a.x + off[r], g.Vp, (unsigned)site, p);
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -184,13 +217,14 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
                               diag * p[sp][c].y - (R)0.5 * acc[r][sp][c].y);
                 R s = (HW && sp >= 2) ? -sc : sc;
                 v = cscale(v, s);
-                const long k = (long)(sp * 3 + c) * g.Vp + site;
+                const size_t po = off[r] + (size_t)(sp * 3 + c) * (unsigned)g.Vp;
+                const unsigned us = (unsigned)site;
                 if (EPI) {
-                    if (a.e1) { cx<R> e = ldc<R>(a.e1 + off[r], k); v.x = fma(c1, e.x, v.x); v.y = fma(c1, e.y, v.y); }
-                    if (a.e2) { cx<R> e = ldc<R>(a.e2 + off[r], k); v.x = fma(c2, e.x, v.x); v.y = fma(c2, e.y, v.y); }
-                    if (a.e3) { cx<R> e = ldc<R>(a.e3 + off[r], k); v.x = fma(c3, e.x, v.x); v.y = fma(c3, e.y, v.y); }
+                    if (a.e1) { cx<R> e = ldp<S, R>(a.e1 + po, us); v.x = fma(c1, e.x, v.x); v.y = fma(c1, e.y, v.y); }
+                    if (a.e2) { cx<R> e = ldp<S, R>(a.e2 + po, us); v.x = fma(c2, e.x, v.x); v.y = fma(c2, e.y, v.y); }
+                    if (a.e3) { cx<R> e = ldp<S, R>(a.e3 + po, us); v.x = fma(c3, e.x, v.x); v.y = fma(c3, e.y, v.y); }
                 }
-                stc<R>(a.y + off[r], k, v);
+                stp<S, R>(a.y + po, us, v);
             }
     }
 }

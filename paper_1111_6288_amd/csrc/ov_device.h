@@ -6,7 +6,10 @@
 // wavefront of 64 consecutive sites reads 64 consecutive complex numbers per
 // load.  A batch of fields is a sequence of such fields, `fstride` storage
 // elements apart.  Links are 4*9 planes [mu][3*a+b][Vp].  Vp is V rounded up
-// to a multiple of 64 and the padding holds zeros.
+// to a multiple of 64.  Invariant: the padding sites V..Vp-1 of every field
+// hold zeros.  Kernels that reduce or combine whole planes (dots, linear
+// combinations, projections) rely on it, so every kernel that writes a field
+// writes zeros there (the workspace is reused across precisions and calls).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -114,6 +117,40 @@ __device__ __forceinline__ cx<R> ldc(const uint32_t *p, long i)
 {
     uint32_t v = p[i];
     return {(R)bf16_lo(v), (R)bf16_hi(v)};
+}
+
+template <class R>
+__device__ __forceinline__ cx<R> ldc(const double2 *p, unsigned i)
+{
+    double2 v = p[i];
+    return {(R)v.x, (R)v.y};
+}
+template <class R>
+__device__ __forceinline__ cx<R> ldc(const float2 *p, unsigned i)
+{
+    float2 v = p[i];
+    return {(R)v.x, (R)v.y};
+}
+template <class R>
+__device__ __forceinline__ cx<R> ldc(const uint32_t *p, unsigned i)
+{
+    uint32_t v = p[i];
+    return {(R)bf16_lo(v), (R)bf16_hi(v)};
+}
+template <class R>
+__device__ __forceinline__ void stc(double2 *p, unsigned i, cx<R> v)
+{
+    p[i] = make_double2((double)v.x, (double)v.y);
+}
+template <class R>
+__device__ __forceinline__ void stc(float2 *p, unsigned i, cx<R> v)
+{
+    p[i] = make_float2((float)v.x, (float)v.y);
+}
+template <class R>
+__device__ __forceinline__ void stc(uint32_t *p, unsigned i, cx<R> v)
+{
+    p[i] = f2bf((float)v.x) | (f2bf((float)v.y) << 16);
 }
 
 template <class R>

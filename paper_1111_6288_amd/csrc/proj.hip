@@ -18,10 +18,14 @@ namespace ov {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // --------------------------------------------------------------- V^dag X (MFMA)
+// Lane layout of v_mfma_f64_16x16x4f64 (D = A B + C, A 16x4, B 4x16), as
+// measured on gfx950: A[i][k] comes from lane i + 16k, B[k][j] from lane
+// j + 16k, and D[i][j] lands in lane j + 16 (i mod 4), register i div 4; so
+// lane q, register r holds row 4r + q/16, column q%16.
+//
 // Workgroup = 4 waves; it owns one K-chunk.  Wave w owns vector tiles
 // w, w+4, ... (up to MT tiles) and all RHS tiles (up to NT).  Per MFMA step
-// lane q holds A[i = q%16][k = q/16] = V and B[k = q/16][j = q%16] = X;
-// the 16x16 result sits in 4 doubles per lane: row 4*(q/16)+r, column q%16.
+// lane q holds A[i = q%16][k = q/16] = V and B[k = q/16][j = q%16] = X.
 template <class S, int MT, int NT>
 __global__ __launch_bounds__(256) void k_proj_dot_mfma(const double2 *__restrict__ V, int l, long vstride,
                                                        const S *__restrict__ X, long xstride,
@@ -95,7 +99,7 @@ __global__ __launch_bounds__(256) void k_proj_dot_mfma(const double2 *__restrict
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = (wave + 4 * m) * 16 + 4 * kq + r;
+                const int i = (wave + 4 * m) * 16 + 4 * r + kq;
                 const int j = t * 16 + row;
                 if (i < l && j < n) pc[(long)j * l + i] = make_double2(cre[m][t][r], cim[m][t][r]);
             }
@@ -118,7 +122,7 @@ __global__ void k_proj_reduce(const double2 *__restrict__ part, int nchunk, int 
 // --------------------------------------------------------------- X + V E (MFMA)
 // Y = alpha X + beta (V E).  Output tile D[j][k] (16 RHS x 16 consecutive k) += A[j][i] B[i][k] with
 // A = E (transposed coefficients) and B = V; lane q holds A[j = q%16][i = q/16]
-// and B[i = q/16][k = q%16]; the result row j = 4*(q/16)+r, column k = q%16,
+// and B[i = q/16][k = q%16]; the result row j = 4r + q/16, column k = q%16,
 // so a store instruction writes four runs of 16 consecutive k.
 // Each wave owns 16 consecutive k (one column block) and NT RHS tiles.
 template <class SX, class SY, int NT>
@@ -159,7 +163,7 @@ __global__ __launch_bounds__(256) void k_proj_expand_mfma(const double2 *__restr
     for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int j = t * 16 + 4 * iq + r;
+            const int j = t * 16 + 4 * r + iq;
             if (j < n && kok) {
                 const int s = slots ? slots[j] : j;
                 cx<double> y = {beta * dre[t][r], beta * dim[t][r]};

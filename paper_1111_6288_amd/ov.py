@@ -59,6 +59,7 @@ def _load():
         "ov_last_error": ([vp], C.c_char_p),
         "ov_upload_gauge": ([vp, vp], i),
         "ov_set_fields": ([vp, i, cp(d), cp(d)], i),
+        "ov_set_field_eta": ([vp, i, d, d], i),
         "ov_set_sign_params": ([vp, i, d, d, cp(d)], i),
         "ov_upload_eigvecs": ([vp, i, i, vp, cp(d)], i),
         "ov_upload_deflation": ([vp, i, i, vp], i),
@@ -73,6 +74,7 @@ def _load():
         "ov_get_tuning": ([vp, i, cp(i), cp(i)], i),
         "ov_autotune": ([vp, i, i, C.c_char_p], i),
         "ov_memory_used": ([vp, cp(C.c_int64)], i),
+        "ov_set_graphs": ([vp, i], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -83,9 +85,10 @@ def _load():
 
 lib = _load()
 EXPORTED = ("ov_create", "ov_destroy", "ov_set_stream", "ov_last_error", "ov_upload_gauge", "ov_set_fields",
+            "ov_set_field_eta",
             "ov_set_sign_params", "ov_upload_eigvecs", "ov_upload_deflation", "ov_dslash", "ov_sign_apply",
             "ov_dov_apply", "ov_deflated_cg", "ov_sign_backward", "ov_prof_enable", "ov_prof_query",
-            "ov_set_tuning", "ov_get_tuning", "ov_autotune", "ov_memory_used")
+            "ov_set_tuning", "ov_get_tuning", "ov_autotune", "ov_memory_used", "ov_set_graphs")
 
 
 def _ints(v):
@@ -149,6 +152,9 @@ class Context:
         self.stream = stream
         return self._chk(lib.ov_set_stream(self._h, C.c_void_p(stream.cuda_stream)))
 
+    def set_graphs(self, on):
+        return self._chk(lib.ov_set_graphs(self._h, int(bool(on))))
+
     def memory_used(self):
         b = C.c_int64()
         self._chk(lib.ov_memory_used(self._h, C.byref(b)))
@@ -161,6 +167,9 @@ class Context:
     def set_fields(self, q, eta):
         q, eta = list(q), list(eta)
         return self._chk(lib.ov_set_fields(self._h, len(q), _doubles(q), _doubles(eta)))
+
+    def set_field_eta(self, field, q, eta):
+        return self._chk(lib.ov_set_field_eta(self._h, int(field), float(q), float(eta)))
 
     def set_sign_params(self, n, eps, norm=0.0, coeffs=None):
         cp = _doubles(coeffs) if coeffs is not None else None

@@ -130,8 +130,8 @@ def random_orthonormal_torch(L, l: int, seed: int, device, dtype=None):
 
     Draws a seeded complex Gaussian block of shape (l, 12V) with torch's
     generator and orthonormalises its rows by CholeskyQR2 (two rounds of Gram
-    matrix, Cholesky factor, triangular solve), which keeps the work in big
-    matrix products.  The result differs from the numpy variant's numbers and
+    matrix, Cholesky factor, multiplication by the inverse factor), which
+    keeps the work in big matrix products.  The result differs from the numpy variant's numbers and
     is meant for throughput runs where the oracle is not asked for the whole
     field.  Returns a (l, V, 4, 3) complex128 tensor on ``device``.
     """
@@ -145,5 +145,5 @@ def random_orthonormal_torch(L, l: int, seed: int, device, dtype=None):
     for _ in range(2):
         G = A @ A.conj().T                      # (l, l) Gram matrix
         R = torch.linalg.cholesky(G)            # G = R R^H, R lower
-        A = torch.linalg.solve_triangular(R, A, upper=False)
+        A = torch.linalg.inv(R) @ A             # (l, l) inverse, one large product
     return A.reshape(l, V, 4, 3)

