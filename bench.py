@@ -57,6 +57,8 @@ def parse():
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--lsmall", type=int, default=LSMALL)
     p.add_argument("--npoly", type=int, default=NPOLY)
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="also run a plain 4 GiB device copy (3 times) to scale PMC byte counters")
     return p.parse_args()
 
 
@@ -246,6 +248,13 @@ def main():
     }
     print(json.dumps(line), flush=True)
     ctx.close()
+    if args.calibrate_copy:
+        src = torch.empty(4 << 30, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] copy calibration: 3 x 4 GiB device-to-device copies", file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":

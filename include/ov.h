@@ -223,6 +223,10 @@ int ov_prof_query(ov_ctx *ctx, const char *kernel_class, long *launches, double 
  */
 int ov_set_tuning(ov_ctx *ctx, int prec, int rhs_per_thread, int block);
 int ov_get_tuning(ov_ctx *ctx, int prec, int *rhs_per_thread, int *block);
+/* Site order of the dslash launches: 0 = each XCD walks a contiguous run of
+ * time slices; 1 = each XCD walks a z-slab plane by plane (needs Lz % 8 == 0
+ * and V % 64 == 0, otherwise 0 is used).  ov_autotune searches both. */
+int ov_set_site_order(ov_ctx *ctx, int prec, int order);
 int ov_autotune(ov_ctx *ctx, int prec, int nrhs, const char *cache_path);
 
 /*

@@ -91,6 +91,7 @@ struct ov_ctx {
     // tuning: rhs per thread and block per precision
     int nr[3] = {2, 4, 4};
     int block[3] = {128, 128, 128};
+    int order[3] = {0, 0, 0};
 
     // profiling
     bool prof_on = false;
@@ -406,6 +407,7 @@ int dslash_launch(ov_ctx *c, const Batch &b, const int *fgroup, const S *x, S *y
     d.c2 = c2;
     d.c3 = c3;
     const int P = PrecOf<S>::p;
+    d.order = c->order[P];
     int nr = c->nr[P];
     while (nr > 1 && nr / 2 >= b.n) nr /= 2;
     const bool epi = e1 || e2 || e3;
@@ -1135,6 +1137,16 @@ int ov_set_tuning(ov_ctx *c, int prec, int rhs_per_thread, int block)
     return OV_OK;
 }
 
+int ov_set_site_order(ov_ctx *c, int prec, int order)
+{
+    CHK(check_ctx(c));
+    CHK(check_prec(c, prec));
+    if (order != 0 && order != 1) return fail(c, OV_EINVAL, "site order must be 0 or 1");
+    invalidate_graphs(c);
+    c->order[prec] = order;
+    return OV_OK;
+}
+
 int ov_get_tuning(ov_ctx *c, int prec, int *rhs_per_thread, int *block)
 {
     CHK(check_ctx(c));
@@ -1703,15 +1715,18 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
         HIPCHK(hipEventCreate(&e9));
         const int nrs[4] = {1, 2, 4, 8}, blks[3] = {64, 128, 256};
         float best = 1e30f;
-        int bnr = c->nr[prec], bbl = c->block[prec];
+        int bnr = c->nr[prec], bbl = c->block[prec], bor = c->order[prec];
         const bool was = c->prof_on;
         c->prof_on = false;
+        const int norders = (c->g.Lz % 8 == 0 && c->g.V % 64 == 0) ? 2 : 1;
+        for (int od = 0; od < norders; ++od)
         for (int nr : nrs) {
             if (nr > 1 && nr / 2 >= nrhs) continue;
             if (prec == OV_FP64 && nr == 8) continue;
             for (int bl : blks) {
                 c->nr[prec] = nr;
                 c->block[prec] = bl;
+                c->order[prec] = od;
                 for (int rep = 0; rep < 2; ++rep)
                     CHK(dslash_launch<S>(c, b, fg, x, y, 1.0, true, e1, 0.5, e2, -0.5, e3, -1.0));
                 HIPCHK(hipEventRecord(e0, c->stream));
@@ -1726,6 +1741,7 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
                     best = ms;
                     bnr = nr;
                     bbl = bl;
+                    bor = od;
                 }
             }
         }
@@ -1733,6 +1749,7 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
         invalidate_graphs(c);
         c->nr[prec] = bnr;
         c->block[prec] = bbl;
+        c->order[prec] = bor;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e9);
         if (cache_path) {
@@ -1740,8 +1757,8 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
             if (fp) {
                 std::fprintf(fp,
                              "{\"arch\": \"gfx950\", \"L\": [%d, %d, %d, %d], \"prec\": %d, \"nrhs\": %d, "
-                             "\"rhs_per_thread\": %d, \"block\": %d, \"ms_per_launch\": %.6f}\n",
-                             c->L[0], c->L[1], c->L[2], c->L[3], prec, nrhs, bnr, bbl, best / 5.0);
+                             "\"rhs_per_thread\": %d, \"block\": %d, \"site_order\": %d, \"ms_per_launch\": %.6f}\n",
+                             c->L[0], c->L[1], c->L[2], c->L[3], prec, nrhs, bnr, bbl, bor, best / 5.0);
                 std::fclose(fp);
             }
         }

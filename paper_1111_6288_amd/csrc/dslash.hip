@@ -142,13 +142,33 @@ __device__ __forceinline__ int xcd_block(int b, int nblk)
     return (b & 7) * per + (b >> 3);
 }
 
+// Site of this thread.  order 0: blocks walk the sites in canonical order,
+// each XCD taking a contiguous run (t-chunks).  order 1: XCD x owns the
+// z-slab [x Lz/8, (x+1) Lz/8) and walks it plane by plane, (z, t) planes of
+// Lx*Ly sites in t-major order, so the cross-section an XCD sweeps is 1/8 of
+// a time slice and t-neighbours are re-read soon after their first use.
+// order 1 needs Lz % 8 == 0 and V % 64 == 0 (no padding); the launcher checks.
+__device__ __forceinline__ int dslash_site(const Geo &g, int order, int xcd_remap)
+{
+    if (order == 1) {
+        const int xcd = blockIdx.x & 7;
+        const int u = (blockIdx.x >> 3) * blockDim.x + threadIdx.x;
+        const int nz = g.Lz >> 3;
+        const int q = u / g.Lxy, o = u - q * g.Lxy;
+        if (q >= nz * g.Lt) return g.Vp;   // beyond the slab: no work
+        const int zl = q % nz, t = q / nz;
+        return o + g.Lxy * (xcd * nz + zl + g.Lz * t);
+    }
+    const int blk = xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+    return blk * blockDim.x + threadIdx.x;
+}
+
 template <class S, int NR, bool HW, bool EPI>
 __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
 {
     using R = typename StoreT<S>::real;
     const Geo &g = a.g;
-    const int blk = a.xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-    const int site = blk * blockDim.x + threadIdx.x;
+    const int site = dslash_site(g, a.order, a.xcd_remap);
     if (site >= g.Vp) return;
     const int j0 = blockIdx.y * NR;
 
@@ -235,7 +255,11 @@ static hipError_t launch_nr(const DsArgs<S> &a, bool hw, bool epi, int block, hi
     int nbx = (a.g.V + block - 1) / block;
     DsArgs<S> b = a;
     b.xcd_remap = 0;
-    if (nbx >= 64) {          // pad to a multiple of 8 for the XCD remap
+    if (b.order == 1 && (a.g.Lz % 8 != 0 || a.g.V % 64 != 0)) b.order = 0;
+    if (b.order == 1) {
+        const int per_xcd = (a.g.Lz / 8) * a.g.Lt * a.g.Lxy;
+        nbx = 8 * ((per_xcd + block - 1) / block);
+    } else if (nbx >= 64) {   // pad to a multiple of 8 for the XCD remap
         nbx = (nbx + 7) & ~7;
         b.xcd_remap = 1;
     }

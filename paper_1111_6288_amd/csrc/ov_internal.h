@@ -25,6 +25,7 @@ struct DsArgs {
     double a;                // scale of G D_w x
     const S *e1, *e2, *e3;   // epilogue inputs at the own site (same fstride), NULL if unused
     double c1, c2, c3;
+    int order;               // site order: 0 canonical t-chunks per XCD, 1 z-slabs per XCD
     int xcd_remap;           // set by the launcher
 };
 

@@ -87,6 +87,23 @@ def test_dslash_every_tuning_variant(nr, block):
             assert _rel(y[j], api.dslash(lat, x[j], 1)) < tol
 
 
+@pytest.mark.parametrize("nr", [1, 4])
+def test_dslash_zslab_site_order(nr):
+    """Site order 1 (each XCD walks a z-slab) gives the oracle's answer, with padding-free V."""
+    L, bc = (4, 6, 8, 6), (2, 0, 0, 2)
+    U = synth.su3_links(L, 0.5, 17)
+    ctx = make_ctx(L, bc, U, (2 / 3, -1 / 3), (0.2, 0.1))
+    x = synth.gaussian_spinors(L, 5, 2)
+    f = [0, 1, 1, 0, 1]
+    for prec, tol in (("fp32", 2e-6), ("fp64", 1e-14)):
+        ctx.set_tuning(prec, nr, 64)
+        ctx.set_site_order(prec, 1)
+        y = _np(ctx.dslash(_t(x), f, prec=prec))
+        for j in range(5):
+            lat = api.Lattice(L, bc, MW, U, (2 / 3, -1 / 3)[f[j]] * (0.2, 0.1)[f[j]])
+            assert _rel(y[j], api.dslash(lat, x[j], 1)) < tol
+
+
 def test_dslash_deterministic_and_batch_equals_single():
     L, bc = (4, 4, 4, 8), (0, 0, 0, 1)
     U = synth.su3_links(L, 0.4, 3)
