@@ -225,8 +225,15 @@ int ov_set_tuning(ov_ctx *ctx, int prec, int rhs_per_thread, int block);
 int ov_get_tuning(ov_ctx *ctx, int prec, int *rhs_per_thread, int *block);
 /* Site order of the dslash launches: 0 = each XCD walks a contiguous run of
  * time slices; 1 = each XCD walks a z-slab plane by plane (needs Lz % 8 == 0
- * and V % 64 == 0, otherwise 0 is used).  ov_autotune searches both. */
+ * and V % 64 == 0); 2 = every thread owns one (x, y, z) site and one RHS and
+ * marches along t, keeping the time neighbours in registers (needs
+ * V % 64 == 0).  Where a requirement fails, order 0 is used.  ov_autotune
+ * searches all three. */
 int ov_set_site_order(ov_ctx *ctx, int prec, int order);
+/* Cap on resident dslash workgroups per CU (0 = no cap).  A small cap keeps
+ * the set of sites in flight narrow enough for stencil neighbours to be
+ * re-read from L2 instead of HBM. */
+int ov_set_occupancy(ov_ctx *ctx, int prec, int blocks_per_cu);
 int ov_autotune(ov_ctx *ctx, int prec, int nrhs, const char *cache_path);
 
 /*

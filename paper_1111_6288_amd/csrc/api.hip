@@ -92,6 +92,7 @@ struct ov_ctx {
     int nr[3] = {2, 4, 4};
     int block[3] = {128, 128, 128};
     int order[3] = {0, 0, 0};
+    int cap[3] = {0, 0, 0};
 
     // profiling
     bool prof_on = false;
@@ -408,6 +409,12 @@ int dslash_launch(ov_ctx *c, const Batch &b, const int *fgroup, const S *x, S *y
     d.c3 = c3;
     const int P = PrecOf<S>::p;
     d.order = c->order[P];
+    d.blocks_per_cu = c->cap[P];
+    if (d.order == 2) {   // t-chunks: enough workgroups to fill the GPU, chunks of at least 4
+        const long per_chunk = (long)c->g.Lz * ((c->g.Lxy + 63) / 64) * ((b.n + 3) / 4);
+        int nch = (int)std::max(1L, std::min((long)c->g.Lt / 4, (4096 + per_chunk - 1) / per_chunk));
+        d.tchunk = (c->g.Lt + nch - 1) / nch;
+    }
     int nr = c->nr[P];
     while (nr > 1 && nr / 2 >= b.n) nr /= 2;
     const bool epi = e1 || e2 || e3;
@@ -1141,9 +1148,19 @@ int ov_set_site_order(ov_ctx *c, int prec, int order)
 {
     CHK(check_ctx(c));
     CHK(check_prec(c, prec));
-    if (order != 0 && order != 1) return fail(c, OV_EINVAL, "site order must be 0 or 1");
+    if (order < 0 || order > 2) return fail(c, OV_EINVAL, "site order must be 0, 1 or 2");
     invalidate_graphs(c);
     c->order[prec] = order;
+    return OV_OK;
+}
+
+int ov_set_occupancy(ov_ctx *c, int prec, int blocks_per_cu)
+{
+    CHK(check_ctx(c));
+    CHK(check_prec(c, prec));
+    if (blocks_per_cu < 0 || blocks_per_cu > 32) return fail(c, OV_EINVAL, "blocks_per_cu outside [0, 32]");
+    invalidate_graphs(c);
+    c->cap[prec] = blocks_per_cu;
     return OV_OK;
 }
 
@@ -1718,15 +1735,22 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
         int bnr = c->nr[prec], bbl = c->block[prec], bor = c->order[prec];
         const bool was = c->prof_on;
         c->prof_on = false;
-        const int norders = (c->g.Lz % 8 == 0 && c->g.V % 64 == 0) ? 2 : 1;
-        for (int od = 0; od < norders; ++od)
+        const bool slab_ok = c->g.Lz % 8 == 0 && c->g.V % 64 == 0;
+        const int caps[3] = {0, 2, 4};
+        int bcap = c->cap[prec];
+        for (int od = 0; od < 3; ++od)
+        for (int cp : caps)
         for (int nr : nrs) {
+            if (od == 1 && !slab_ok) continue;
+            if (od == 2 && (c->g.V % 64 != 0 || nr != 1 || cp != 0)) continue;   // t-marching: one shape
             if (nr > 1 && nr / 2 >= nrhs) continue;
             if (prec == OV_FP64 && nr == 8) continue;
             for (int bl : blks) {
+                if (od == 2 && bl != 256) continue;
                 c->nr[prec] = nr;
                 c->block[prec] = bl;
                 c->order[prec] = od;
+                c->cap[prec] = cp;
                 for (int rep = 0; rep < 2; ++rep)
                     CHK(dslash_launch<S>(c, b, fg, x, y, 1.0, true, e1, 0.5, e2, -0.5, e3, -1.0));
                 HIPCHK(hipEventRecord(e0, c->stream));
@@ -1742,6 +1766,7 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
                     bnr = nr;
                     bbl = bl;
                     bor = od;
+                    bcap = cp;
                 }
             }
         }
@@ -1750,6 +1775,7 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
         c->nr[prec] = bnr;
         c->block[prec] = bbl;
         c->order[prec] = bor;
+        c->cap[prec] = bcap;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e9);
         if (cache_path) {
@@ -1757,8 +1783,9 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
             if (fp) {
                 std::fprintf(fp,
                              "{\"arch\": \"gfx950\", \"L\": [%d, %d, %d, %d], \"prec\": %d, \"nrhs\": %d, "
-                             "\"rhs_per_thread\": %d, \"block\": %d, \"site_order\": %d, \"ms_per_launch\": %.6f}\n",
-                             c->L[0], c->L[1], c->L[2], c->L[3], prec, nrhs, bnr, bbl, bor, best / 5.0);
+                             "\"rhs_per_thread\": %d, \"block\": %d, \"site_order\": %d, \"blocks_per_cu\": %d, "
+                             "\"ms_per_launch\": %.6f}\n",
+                             c->L[0], c->L[1], c->L[2], c->L[3], prec, nrhs, bnr, bbl, bor, bcap, best / 5.0);
                 std::fclose(fp);
             }
         }

@@ -249,9 +249,189 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// t-marching variant.  Each thread owns one (x, y, z) site and one RHS and
+// walks t over a chunk [t0, t1), keeping psi(t-1), psi(t), psi(t+1) and the
+// backward time link in registers: the two time neighbours cost no loads and
+// every input spinor is fetched once per chunk.  A wave covers 64 consecutive
+// sites of one (z, t) plane, so x and y neighbours come from lines the wave
+// itself touches in the same step (L1); the 4 waves of a workgroup are 4 RHS
+// on the same sites, so link loads are shared through L1; blocks walk z
+// fastest within an XCD, so z neighbours are loaded by workgroups running at
+// the same time on the same XCD (L2).
+//
+// Block b: XCD b & 7, local index m = b >> 3 decomposed as
+//   m = z + Lz (ob + nob (tc + ntc rg))
+// with ob the 64-site block of the (x, y) plane, tc the t-chunk and rg the
+// group of 4 RHS.  Needs V % 64 == 0 (no padding); the launcher checks.
+template <class S, bool HW, bool EPI>
+__global__ __launch_bounds__(256) void k_dslash_tm(DsArgs<S> a)
+{
+    using R = typename StoreT<S>::real;
+    const Geo &g = a.g;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nob = (g.Lxy + 63) >> 6;
+    const int ntc = (g.Lt + a.tchunk - 1) / a.tchunk;
+    // XCD k takes the contiguous range of m starting at k * gridDim.x / 8; its
+    // successive blocks walk z fastest
+    int m = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    const int z = m % g.Lz;
+    m /= g.Lz;
+    const int ob = m % nob;
+    m /= nob;
+    const int tc = m % ntc;
+    const int rg = m / ntc;
+    const int j = rg * 4 + wave;
+    const int o = ob * 64 + lane;
+    if (j >= a.n || o >= g.Lxy) return;
+
+    const int s = __builtin_amdgcn_readfirstlane(a.slots ? a.slots[j] : j);
+    const size_t off = (size_t)s * (size_t)a.fstride;
+    const int grp = __builtin_amdgcn_readfirstlane(a.fgroup ? a.fgroup[s] : 0);
+    const int xc = o % g.Lx, yc = o / g.Lx;
+    const int t0 = tc * a.tchunk;
+    const int t1 = (t0 + a.tchunk < g.Lt) ? t0 + a.tchunk : g.Lt;
+    const int Vp = g.Vp;
+    const int base_zt = o + g.Lxy * z;          // site of (x, y, z, t) = base_zt + Lxyz t
+    const S *x = a.x + off;
+
+    auto site_at = [&](int t) { return base_zt + g.Lxyz * t; };
+    const int tm1 = (t0 == 0) ? g.Lt - 1 : t0 - 1;
+
+    cx<R> pm[4][3], pc[4][3], pn[4][3], utm[3][3];
+    load_spinor<S, R>(x, Vp, (unsigned)site_at(tm1), pm);
+    load_spinor<S, R>(x, Vp, (unsigned)site_at(t0), pc);
+    load_link<S, R>(a.U, 3, Vp, (unsigned)site_at(tm1), utm);
+
+    const size_t offs[1] = {off};
+    const bool acts[1] = {true};
+    const R diag = (R)a.diag, sc = (R)a.a;
+    const R c1 = (R)a.c1, c2 = (R)a.c2, c3 = (R)a.c3;
+    const R bt = (R)g.bcf[3];
+
+    for (int t = t0; t < t1; ++t) {
+        const int site = site_at(t);
+        const int tp1 = (t == g.Lt - 1) ? 0 : t + 1;
+        load_spinor<S, R>(x, Vp, (unsigned)site_at(tp1), pn);
+        cx<R> utc[3][3];
+        load_link<S, R>(a.U, 3, Vp, (unsigned)site, utc);
+        const cx<double> pd = a.phase[grp * g.Lt + t];
+        const cx<R> ph[1] = {cmk((R)pd.x, (R)pd.y)};
+
+        cx<R> acc[1][4][3];
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[0][sp][c] = cmk((R)0, (R)0);
+
+        hop_dir<0, 1, S, R>(a, site, xc, g.Lx, 1, offs, acts, ph, acc);
+        hop_dir<1, 1, S, R>(a, site, yc, g.Ly, g.Lx, offs, acts, ph, acc);
+        hop_dir<2, 1, S, R>(a, site, z, g.Lz, g.Lxy, offs, acts, ph, acc);
+
+        // time hops from registers
+        {
+            const R bf = (t == g.Lt - 1) ? bt : (R)1;
+            if (bf != (R)0) {
+                cx<R> h[2][3], gg[2][3];
+                project<3, -1>(pn, h);
+                if (bf != (R)1) {
+#pragma unroll
+                    for (int k = 0; k < 2; ++k)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) h[k][c] = cscale(h[k][c], bf);
+                }
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int aa = 0; aa < 3; ++aa) {
+                        cx<R> tt = cmul(utc[aa][0], h[k][0]);
+                        cfma(tt, utc[aa][1], h[k][1]);
+                        cfma(tt, utc[aa][2], h[k][2]);
+                        gg[k][aa] = tt;
+                    }
+                expand_add<3, -1>(acc[0], gg);
+            }
+            const R bb = (t == 0) ? bt : (R)1;
+            if (bb != (R)0) {
+                cx<R> h[2][3], gg[2][3];
+                project<3, +1>(pm, h);
+                if (bb != (R)1) {
+#pragma unroll
+                    for (int k = 0; k < 2; ++k)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) h[k][c] = cscale(h[k][c], bb);
+                }
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int aa = 0; aa < 3; ++aa) {
+                        cx<R> tt = cmulc(utm[0][aa], h[k][0]);
+                        cfmac(tt, utm[1][aa], h[k][1]);
+                        cfmac(tt, utm[2][aa], h[k][2]);
+                        gg[k][aa] = tt;
+                    }
+                expand_add<3, +1>(acc[0], gg);
+            }
+        }
+
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                cx<R> v = cmk(diag * pc[sp][c].x - (R)0.5 * acc[0][sp][c].x,
+                              diag * pc[sp][c].y - (R)0.5 * acc[0][sp][c].y);
+                const R sg = (HW && sp >= 2) ? -sc : sc;
+                v = cscale(v, sg);
+                const size_t po = off + (size_t)(sp * 3 + c) * (unsigned)Vp;
+                if (EPI) {
+                    if (a.e1) { cx<R> e = ldp<S, R>(a.e1 + po, (unsigned)site); v.x = fma(c1, e.x, v.x); v.y = fma(c1, e.y, v.y); }
+                    if (a.e2) { cx<R> e = ldp<S, R>(a.e2 + po, (unsigned)site); v.x = fma(c2, e.x, v.x); v.y = fma(c2, e.y, v.y); }
+                    if (a.e3) { cx<R> e = ldp<S, R>(a.e3 + po, (unsigned)site); v.x = fma(c3, e.x, v.x); v.y = fma(c3, e.y, v.y); }
+                }
+                stp<S, R>(a.y + po, (unsigned)site, v);
+            }
+
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                pm[sp][c] = pc[sp][c];
+                pc[sp][c] = pn[sp][c];
+            }
+#pragma unroll
+        for (int aa = 0; aa < 3; ++aa)
+#pragma unroll
+            for (int bb2 = 0; bb2 < 3; ++bb2) utm[aa][bb2] = utc[aa][bb2];
+    }
+}
+
+template <class S>
+static hipError_t launch_tm(const DsArgs<S> &a, bool hw, bool epi, hipStream_t st)
+{
+    DsArgs<S> b = a;
+    if (b.tchunk <= 0 || b.tchunk > a.g.Lt) b.tchunk = a.g.Lt;
+    const int nob = (a.g.Lxy + 63) / 64;
+    const int ntc = (a.g.Lt + b.tchunk - 1) / b.tchunk;
+    const long nblk = (long)a.g.Lz * nob * ntc * ((a.n + 3) / 4);
+    const long padded = (nblk + 7) / 8 * 8;
+    if (padded > 0x7fffffffL) return hipErrorInvalidValue;
+    if (epi)
+        hipLaunchKernelGGL((k_dslash_tm<S, true, true>), dim3((unsigned)padded), dim3(256), 0, st, b);
+    else if (hw)
+        hipLaunchKernelGGL((k_dslash_tm<S, true, false>), dim3((unsigned)padded), dim3(256), 0, st, b);
+    else
+        hipLaunchKernelGGL((k_dslash_tm<S, false, false>), dim3((unsigned)padded), dim3(256), 0, st, b);
+    return hipGetLastError();
+}
+
 template <class S, int NR>
 static hipError_t launch_nr(const DsArgs<S> &a, bool hw, bool epi, int block, hipStream_t st)
 {
+    // Occupancy cap: reserving LDS the kernel does not use limits the number of
+    // resident workgroups per CU (160 KiB of LDS per CU on gfx950), which
+    // narrows the window of sites in flight so that stencil neighbours are
+    // re-read while still in L2.
+    const size_t lds = a.blocks_per_cu > 0 ? (size_t)(160 * 1024) / (size_t)a.blocks_per_cu - 256 : 0;
     int nbx = (a.g.V + block - 1) / block;
     DsArgs<S> b = a;
     b.xcd_remap = 0;
@@ -264,12 +444,27 @@ static hipError_t launch_nr(const DsArgs<S> &a, bool hw, bool epi, int block, hi
         b.xcd_remap = 1;
     }
     dim3 grid(nbx, (a.n + NR - 1) / NR);
+    if (lds > 0) {   // allow more than the default 64 KiB of dynamic LDS (once per kernel)
+        static bool raised[3] = {false, false, false};
+        const int ki = epi ? 0 : (hw ? 1 : 2);
+        if (!raised[ki]) {
+            hipError_t e;
+            if (epi) e = hipFuncSetAttribute((const void *)k_dslash<S, NR, true, true>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            else if (hw) e = hipFuncSetAttribute((const void *)k_dslash<S, NR, true, false>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            else e = hipFuncSetAttribute((const void *)k_dslash<S, NR, false, false>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e != hipSuccess) return e;
+            raised[ki] = true;
+        }
+    }
     if (epi)
-        hipLaunchKernelGGL((k_dslash<S, NR, true, true>), grid, dim3(block), 0, st, b);
+        hipLaunchKernelGGL((k_dslash<S, NR, true, true>), grid, dim3(block), lds, st, b);
     else if (hw)
-        hipLaunchKernelGGL((k_dslash<S, NR, true, false>), grid, dim3(block), 0, st, b);
+        hipLaunchKernelGGL((k_dslash<S, NR, true, false>), grid, dim3(block), lds, st, b);
     else
-        hipLaunchKernelGGL((k_dslash<S, NR, false, false>), grid, dim3(block), 0, st, b);
+        hipLaunchKernelGGL((k_dslash<S, NR, false, false>), grid, dim3(block), lds, st, b);
     return hipGetLastError();
 }
 
@@ -278,6 +473,7 @@ hipError_t launch_dslash(const DsArgs<S> &a, bool hw, bool epi, int nr, int bloc
 {
     if (a.n <= 0) return hipSuccess;
     if (block < 64 || block > 256 || (block & 63)) return hipErrorInvalidValue;
+    if (a.order == 2 && a.g.V % 64 == 0) return launch_tm<S>(a, hw, epi, st);
     switch (nr) {
     case 1: return launch_nr<S, 1>(a, hw, epi, block, st);
     case 2: return launch_nr<S, 2>(a, hw, epi, block, st);

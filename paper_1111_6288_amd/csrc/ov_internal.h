@@ -25,7 +25,9 @@ struct DsArgs {
     double a;                // scale of G D_w x
     const S *e1, *e2, *e3;   // epilogue inputs at the own site (same fstride), NULL if unused
     double c1, c2, c3;
-    int order;               // site order: 0 canonical t-chunks per XCD, 1 z-slabs per XCD
+    int order;               // 0 canonical t-chunks per XCD, 1 z-slabs per XCD, 2 t-marching threads
+    int tchunk;              // t-chunk length of order 2 (0: whole Lt)
+    int blocks_per_cu;       // occupancy cap (0: none), enforced through reserved LDS
     int xcd_remap;           // set by the launcher
 };
 

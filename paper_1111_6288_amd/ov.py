@@ -76,6 +76,7 @@ def _load():
         "ov_memory_used": ([vp, cp(C.c_int64)], i),
         "ov_set_graphs": ([vp, i], i),
         "ov_set_site_order": ([vp, i, i], i),
+        "ov_set_occupancy": ([vp, i, i], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -90,7 +91,7 @@ EXPORTED = ("ov_create", "ov_destroy", "ov_set_stream", "ov_last_error", "ov_upl
             "ov_set_sign_params", "ov_upload_eigvecs", "ov_upload_deflation", "ov_dslash", "ov_sign_apply",
             "ov_dov_apply", "ov_deflated_cg", "ov_sign_backward", "ov_prof_enable", "ov_prof_query",
             "ov_set_tuning", "ov_get_tuning", "ov_autotune", "ov_memory_used", "ov_set_graphs",
-            "ov_set_site_order")
+            "ov_set_site_order", "ov_set_occupancy")
 
 
 def _ints(v):
@@ -262,6 +263,9 @@ class Context:
 
     def set_site_order(self, prec, order):
         return self._chk(lib.ov_set_site_order(self._h, PREC[prec], int(order)))
+
+    def set_occupancy(self, prec, blocks_per_cu):
+        return self._chk(lib.ov_set_occupancy(self._h, PREC[prec], int(blocks_per_cu)))
 
     def get_tuning(self, prec):
         a, b = C.c_int(), C.c_int()

@@ -104,6 +104,44 @@ def test_dslash_zslab_site_order(nr):
             assert _rel(y[j], api.dslash(lat, x[j], 1)) < tol
 
 
+@pytest.mark.parametrize("L,bc", [((4, 4, 4, 4), (0, 0, 0, 1)), ((4, 6, 8, 6), (2, 0, 0, 2)),
+                                  ((8, 8, 8, 16), (1, 2, 0, 0))])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-14), ("fp32", 2e-6), ("bf16", 2e-2)])
+def test_dslash_tmarch_order(L, bc, prec, tol):
+    """Site order 2 (threads march along t with the time neighbours in registers)."""
+    U = synth.su3_links(L, 0.5, 23)
+    q, eta = (2 / 3, -1 / 3, 2 / 3), (0.0, 0.31, -0.12)
+    ctx = make_ctx(L, bc, U, q, eta)
+    ctx.set_site_order(prec, 2)
+    x = synth.gaussian_spinors(L, 7, 5)
+    fields = [j % 3 for j in range(7)]
+    for op, opc in (("HW", 1), ("DW", 0)):
+        y = _np(ctx.dslash(_t(x), fields, op=op, prec=prec))
+        for j in range(7):
+            lat = api.Lattice(L, bc, MW, U, q[fields[j]] * eta[fields[j]])
+            assert _rel(y[j], api.dslash(lat, x[j], opc)) < tol, (op, j)
+
+
+def test_sign_with_tmarch_order():
+    """The fused Clenshaw epilogue under site order 2."""
+    L, bc = (8, 8, 8, 16), (2, 0, 0, 2)
+    U = synth.su3_links(L, 0.2, 77)
+    ctx = make_ctx(L, bc, U, (2 / 3,), (1e-3,))
+    n = 60
+    eps = 0.5 / n ** 2
+    ctx.set_sign_params(n, eps, 6.5)
+    Vs = synth.random_orthonormal(L, 6, 5)
+    lam = np.linspace(-1, 1, 6)
+    ctx.upload_eigvecs(0, _t(Vs), lam)
+    x = synth.gaussian_spinors(L, 5, 3)
+    ref = api.sign(api.Lattice(L, bc, MW, U, 2 / 3 * 1e-3), api.SignParams(n, eps, 6.5, Vs, lam), x[:2])
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5)):
+        ctx.set_site_order(prec, 2)
+        y = _np(ctx.sign_apply(_t(x), [0] * 5, prec=prec))
+        for j in range(2):
+            assert _rel(y[j], ref[j]) < tol
+
+
 def test_dslash_deterministic_and_batch_equals_single():
     L, bc = (4, 4, 4, 8), (0, 0, 0, 1)
     U = synth.su3_links(L, 0.4, 3)
