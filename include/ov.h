@@ -216,10 +216,15 @@ int ov_prof_query(ov_ctx *ctx, const char *kernel_class, long *launches, double 
 
 /*
  * Kernel launch tuning of the dslash family: RHS per thread (1, 2, 4, 8) and
- * threads per workgroup (64..1024, multiple of 64) for precision prec.
+ * threads per workgroup (64, 128, 192, 256 or 512) for precision prec.  The
+ * t-marching site order (ov_set_site_order 2) ignores rhs_per_thread and
+ * reads block as 64 threads per right-hand side of a workgroup: 512 puts 8
+ * RHS in a workgroup, any other value 4.  The other orders use at most 256.
  * ov_autotune times the candidates on the current context for nrhs RHS,
- * keeps the fastest and, with a non-NULL cache_path, records it there as a
- * one-line JSON object per key.
+ * separately for plain launches and for launches with the fused Clenshaw
+ * epilogue, keeps the fastest of each and, with a non-NULL cache_path,
+ * appends one JSON line per kind there.  ov_get_tuning reports the plain
+ * kind.
  */
 int ov_set_tuning(ov_ctx *ctx, int prec, int rhs_per_thread, int block);
 int ov_get_tuning(ov_ctx *ctx, int prec, int *rhs_per_thread, int *block);
@@ -234,6 +239,16 @@ int ov_set_site_order(ov_ctx *ctx, int prec, int order);
  * the set of sites in flight narrow enough for stencil neighbours to be
  * re-read from L2 instead of HBM. */
 int ov_set_occupancy(ov_ctx *ctx, int prec, int blocks_per_cu);
+/* Launch shape of precision prec for kind 0 (plain H_w / D_w launches) or
+ * kind 1 (launches with the fused Clenshaw epilogue), which ov_autotune tunes
+ * separately; the three setters above set both kinds.  cfg is
+ * {rhs_per_thread, block, site_order, blocks_per_cu, stream_hint}, each with
+ * the meaning and range given above; stream_hint 1 marks the operands a
+ * launch touches once (epilogue inputs, output) non-temporal so that they do
+ * not displace stencil neighbours from L2.  Set: OV_EINVAL on a value out of
+ * range (nothing changed). */
+int ov_get_launch_config(ov_ctx *ctx, int prec, int kind, int cfg[5]);
+int ov_set_launch_config(ov_ctx *ctx, int prec, int kind, const int cfg[5]);
 int ov_autotune(ov_ctx *ctx, int prec, int nrhs, const char *cache_path);
 
 /*

@@ -88,11 +88,11 @@ struct ov_ctx {
     std::map<std::vector<double>, double *> dcache;
     std::map<std::vector<double>, double2 *> ccache;
 
-    // tuning: rhs per thread and block per precision
-    int nr[3] = {2, 4, 4};
-    int block[3] = {128, 128, 128};
-    int order[3] = {0, 0, 0};
-    int cap[3] = {0, 0, 0};
+    // dslash launch shape per precision and kind (0: plain, 1: fused Clenshaw epilogue)
+    struct Launch {
+        int nr = 2, block = 128, order = 0, cap = 0, stream_hint = 0;
+    };
+    Launch tune[3][2];
 
     // profiling
     bool prof_on = false;
@@ -408,18 +408,21 @@ int dslash_launch(ov_ctx *c, const Batch &b, const int *fgroup, const S *x, S *y
     d.c2 = c2;
     d.c3 = c3;
     const int P = PrecOf<S>::p;
-    d.order = c->order[P];
-    d.blocks_per_cu = c->cap[P];
+    const bool epi = e1 || e2 || e3;
+    const auto &tu = c->tune[P][epi ? 1 : 0];
+    d.order = tu.order;
+    d.blocks_per_cu = tu.cap;
+    d.stream_hint = tu.stream_hint;
     if (d.order == 2) {   // t-chunks: enough workgroups to fill the GPU, chunks of at least 4
-        const long per_chunk = (long)c->g.Lz * ((c->g.Lxy + 63) / 64) * ((b.n + 3) / 4);
+        const int W = tu.block == 512 ? 8 : 4;   // right-hand sides per workgroup
+        const long per_chunk = (long)c->g.Lz * ((c->g.Lxy + 63) / 64) * ((b.n + W - 1) / W);
         int nch = (int)std::max(1L, std::min((long)c->g.Lt / 4, (4096 + per_chunk - 1) / per_chunk));
         d.tchunk = (c->g.Lt + nch - 1) / nch;
     }
-    int nr = c->nr[P];
+    int nr = tu.nr;
     while (nr > 1 && nr / 2 >= b.n) nr /= 2;
-    const bool epi = e1 || e2 || e3;
     int pi = prof_begin(c);
-    HIPCHK(launch_dslash<S>(d, hw || epi, epi, nr, c->block[P], c->stream));
+    HIPCHK(launch_dslash<S>(d, hw || epi, epi, nr, tu.block, c->stream));
     const double sb = sizeof(S);
     const int nex = (e1 ? 1 : 0) + (e2 ? 1 : 0) + (e3 ? 1 : 0);
     prof_end(c, pi, epi ? PC_CLENSHAW : PC_DSLASH,
@@ -1137,10 +1140,13 @@ int ov_set_tuning(ov_ctx *c, int prec, int rhs_per_thread, int block)
     CHK(check_prec(c, prec));
     if (rhs_per_thread != 1 && rhs_per_thread != 2 && rhs_per_thread != 4 && rhs_per_thread != 8)
         return fail(c, OV_EINVAL, "rhs_per_thread must be 1, 2, 4 or 8");
-    if (block < 64 || block > 256 || block % 64) return fail(c, OV_EINVAL, "block must be 64, 128, 192 or 256");
+    if (block != 64 && block != 128 && block != 192 && block != 256 && block != 512)
+        return fail(c, OV_EINVAL, "block must be 64, 128, 192, 256 or 512");
     invalidate_graphs(c);
-    c->nr[prec] = rhs_per_thread;
-    c->block[prec] = block;
+    for (auto &tu : c->tune[prec]) {
+        tu.nr = rhs_per_thread;
+        tu.block = block;
+    }
     return OV_OK;
 }
 
@@ -1150,7 +1156,7 @@ int ov_set_site_order(ov_ctx *c, int prec, int order)
     CHK(check_prec(c, prec));
     if (order < 0 || order > 2) return fail(c, OV_EINVAL, "site order must be 0, 1 or 2");
     invalidate_graphs(c);
-    c->order[prec] = order;
+    for (auto &tu : c->tune[prec]) tu.order = order;
     return OV_OK;
 }
 
@@ -1160,7 +1166,45 @@ int ov_set_occupancy(ov_ctx *c, int prec, int blocks_per_cu)
     CHK(check_prec(c, prec));
     if (blocks_per_cu < 0 || blocks_per_cu > 32) return fail(c, OV_EINVAL, "blocks_per_cu outside [0, 32]");
     invalidate_graphs(c);
-    c->cap[prec] = blocks_per_cu;
+    for (auto &tu : c->tune[prec]) tu.cap = blocks_per_cu;
+    return OV_OK;
+}
+
+int ov_get_launch_config(ov_ctx *c, int prec, int kind, int *cfg)
+{
+    CHK(check_ctx(c));
+    CHK(check_prec(c, prec));
+    if (kind != 0 && kind != 1) return fail(c, OV_EINVAL, "kind must be 0 (plain) or 1 (fused epilogue)");
+    if (!cfg) return fail(c, OV_EINVAL, "cfg is NULL");
+    const auto &tu = c->tune[prec][kind];
+    cfg[0] = tu.nr;
+    cfg[1] = tu.block;
+    cfg[2] = tu.order;
+    cfg[3] = tu.cap;
+    cfg[4] = tu.stream_hint;
+    return OV_OK;
+}
+
+int ov_set_launch_config(ov_ctx *c, int prec, int kind, const int *cfg)
+{
+    CHK(check_ctx(c));
+    CHK(check_prec(c, prec));
+    if (kind != 0 && kind != 1) return fail(c, OV_EINVAL, "kind must be 0 (plain) or 1 (fused epilogue)");
+    if (!cfg) return fail(c, OV_EINVAL, "cfg is NULL");
+    const int nr = cfg[0], bl = cfg[1], od = cfg[2], cp = cfg[3], sh = cfg[4];
+    if (nr != 1 && nr != 2 && nr != 4 && nr != 8) return fail(c, OV_EINVAL, "rhs_per_thread must be 1, 2, 4 or 8");
+    if (bl != 64 && bl != 128 && bl != 192 && bl != 256 && bl != 512)
+        return fail(c, OV_EINVAL, "block must be 64, 128, 192, 256 or 512");
+    if (od < 0 || od > 2) return fail(c, OV_EINVAL, "site order must be 0, 1 or 2");
+    if (cp < 0 || cp > 32) return fail(c, OV_EINVAL, "blocks_per_cu outside [0, 32]");
+    if (sh != 0 && sh != 1) return fail(c, OV_EINVAL, "stream_hint must be 0 or 1");
+    invalidate_graphs(c);
+    auto &tu = c->tune[prec][kind];
+    tu.nr = nr;
+    tu.block = bl;
+    tu.order = od;
+    tu.cap = cp;
+    tu.stream_hint = sh;
     return OV_OK;
 }
 
@@ -1168,8 +1212,8 @@ int ov_get_tuning(ov_ctx *c, int prec, int *rhs_per_thread, int *block)
 {
     CHK(check_ctx(c));
     CHK(check_prec(c, prec));
-    if (rhs_per_thread) *rhs_per_thread = c->nr[prec];
-    if (block) *block = c->block[prec];
+    if (rhs_per_thread) *rhs_per_thread = c->tune[prec][0].nr;
+    if (block) *block = c->tune[prec][0].block;
     return OV_OK;
 }
 
@@ -1713,8 +1757,9 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
     CHK(check_prec(c, prec));
     if (!c->have_gauge || c->nfield == 0) return fail(c, OV_ESTATE, "upload the gauge field and fields first");
     if (nrhs < 1 || nrhs > 4096) return fail(c, OV_EINVAL, "nrhs outside [1, 4096]");
-    // Times the fused Clenshaw launch (dslash + epilogue) for every candidate
-    // on synthetic data already in the workspace; keeps the fastest.
+    // Times every candidate launch shape on synthetic data already in the
+    // workspace, separately for the plain H_w launch and the fused Clenshaw
+    // launch (dslash + epilogue), and keeps the fastest of each.
     auto run = [&](auto tag) -> int {
         using S = decltype(tag);
         const size_t fb = align_up(field_bytes<S>(c) * nrhs);
@@ -1730,62 +1775,74 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
         hipEvent_t e0, e9;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e9));
-        const int nrs[4] = {1, 2, 4, 8}, blks[3] = {64, 128, 256};
-        float best = 1e30f;
-        int bnr = c->nr[prec], bbl = c->block[prec], bor = c->order[prec];
+        const int nrs[4] = {1, 2, 4, 8}, blks[4] = {64, 128, 256, 512};
+        const int caps[3] = {0, 2, 4};
         const bool was = c->prof_on;
         c->prof_on = false;
         const bool slab_ok = c->g.Lz % 8 == 0 && c->g.V % 64 == 0;
-        const int caps[3] = {0, 2, 4};
-        int bcap = c->cap[prec];
-        for (int od = 0; od < 3; ++od)
-        for (int cp : caps)
-        for (int nr : nrs) {
-            if (od == 1 && !slab_ok) continue;
-            if (od == 2 && (c->g.V % 64 != 0 || nr != 1 || cp != 0)) continue;   // t-marching: one shape
-            if (nr > 1 && nr / 2 >= nrhs) continue;
-            if (prec == OV_FP64 && nr == 8) continue;
-            for (int bl : blks) {
-                if (od == 2 && bl != 256) continue;
-                c->nr[prec] = nr;
-                c->block[prec] = bl;
-                c->order[prec] = od;
-                c->cap[prec] = cp;
-                for (int rep = 0; rep < 2; ++rep)
-                    CHK(dslash_launch<S>(c, b, fg, x, y, 1.0, true, e1, 0.5, e2, -0.5, e3, -1.0));
-                HIPCHK(hipEventRecord(e0, c->stream));
-                const int reps = 5;
-                for (int rep = 0; rep < reps; ++rep)
-                    CHK(dslash_launch<S>(c, b, fg, x, y, 1.0, true, e1, 0.5, e2, -0.5, e3, -1.0));
-                HIPCHK(hipEventRecord(e9, c->stream));
-                HIPCHK(hipEventSynchronize(e9));
-                float ms = 0;
-                HIPCHK(hipEventElapsedTime(&ms, e0, e9));
-                if (ms < best) {
-                    best = ms;
-                    bnr = nr;
-                    bbl = bl;
-                    bor = od;
-                    bcap = cp;
+        float best_ms[2] = {0, 0};
+        int rc = OV_OK;
+        for (int kind = 0; kind < 2 && rc == OV_OK; ++kind) {
+            auto &tu = c->tune[prec][kind];
+            auto launch = [&]() -> int {
+                if (kind == 0) return dslash_launch<S>(c, b, fg, x, y, 1.0, true);
+                return dslash_launch<S>(c, b, fg, x, y, 1.0, true, e1, 0.5, e2, -0.5, e3, -1.0);
+            };
+            const auto keep = tu;
+            auto bestc = tu;
+            float best = 1e30f;
+            for (int sh = 0; sh < 2 && rc == OV_OK; ++sh)
+            for (int od = 0; od < 3 && rc == OV_OK; ++od)
+            for (int cp : caps)
+            for (int nr : nrs) {
+                if (od == 1 && !slab_ok) continue;
+                if (od == 2 && (c->g.V % 64 != 0 || nr != 1 || cp != 0)) continue;   // t-marching: one shape
+                if (nr > 1 && nr / 2 >= nrhs) continue;
+                if (prec == OV_FP64 && nr == 8) continue;
+                for (int bl : blks) {
+                    if (od != 2 && bl == 512) continue;   // 512 threads: t-marching only
+                    if (od == 2 && bl < 256) continue;    // t-marching: 4 or 8 RHS per workgroup
+                    if (od == 2 && bl == 512 && prec == OV_FP64) continue;   // FP64 needs > 256 VGPRs
+                    tu.nr = nr;
+                    tu.block = bl;
+                    tu.order = od;
+                    tu.cap = cp;
+                    tu.stream_hint = sh;
+                    for (int rep = 0; rep < 2 && rc == OV_OK; ++rep) rc = launch();
+                    if (rc == OV_OK && hipEventRecord(e0, c->stream) != hipSuccess) rc = OV_EHIP;
+                    const int reps = 5;
+                    for (int rep = 0; rep < reps && rc == OV_OK; ++rep) rc = launch();
+                    if (rc == OV_OK && hipEventRecord(e9, c->stream) != hipSuccess) rc = OV_EHIP;
+                    if (rc == OV_OK && hipEventSynchronize(e9) != hipSuccess) rc = OV_EHIP;
+                    float ms = 0;
+                    if (rc == OV_OK && hipEventElapsedTime(&ms, e0, e9) != hipSuccess) rc = OV_EHIP;
+                    if (rc != OV_OK) break;
+                    if (ms < best) {
+                        best = ms;
+                        bestc = tu;
+                    }
                 }
             }
+            tu = rc == OV_OK ? bestc : keep;
+            best_ms[kind] = best / 5.0f;
         }
         c->prof_on = was;
         invalidate_graphs(c);
-        c->nr[prec] = bnr;
-        c->block[prec] = bbl;
-        c->order[prec] = bor;
-        c->cap[prec] = bcap;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e9);
+        if (rc != OV_OK) return rc == OV_EHIP ? fail(c, OV_EHIP, "autotune: HIP event call failed") : rc;
         if (cache_path) {
             FILE *fp = std::fopen(cache_path, "a");
             if (fp) {
-                std::fprintf(fp,
-                             "{\"arch\": \"gfx950\", \"L\": [%d, %d, %d, %d], \"prec\": %d, \"nrhs\": %d, "
-                             "\"rhs_per_thread\": %d, \"block\": %d, \"site_order\": %d, \"blocks_per_cu\": %d, "
-                             "\"ms_per_launch\": %.6f}\n",
-                             c->L[0], c->L[1], c->L[2], c->L[3], prec, nrhs, bnr, bbl, bor, bcap, best / 5.0);
+                for (int kind = 0; kind < 2; ++kind) {
+                    const auto &tu = c->tune[prec][kind];
+                    std::fprintf(fp,
+                                 "{\"arch\": \"gfx950\", \"L\": [%d, %d, %d, %d], \"prec\": %d, \"nrhs\": %d, "
+                                 "\"kind\": \"%s\", \"rhs_per_thread\": %d, \"block\": %d, \"site_order\": %d, "
+                                 "\"blocks_per_cu\": %d, \"stream_hint\": %d, \"ms_per_launch\": %.6f}\n",
+                                 c->L[0], c->L[1], c->L[2], c->L[3], prec, nrhs, kind ? "clenshaw" : "dslash",
+                                 tu.nr, tu.block, tu.order, tu.cap, tu.stream_hint, best_ms[kind]);
+                }
                 std::fclose(fp);
             }
         }

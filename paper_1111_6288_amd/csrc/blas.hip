@@ -9,7 +9,7 @@
 namespace ov {
 
 // ---------------------------------------------------------------- packing
-// canonical complex128 [n][V][4][3]  <->  planes [slot][12][Vp]
+// canonical complex128 [n][V][4][3]  <->  internal field layout [slot]
 template <class S>
 __global__ void k_pack_spinor(const double2 *__restrict__ in, S *__restrict__ out, long fstride,
                               const int *slots, int n, int V, int Vp)
@@ -26,7 +26,7 @@ __global__ void k_pack_spinor(const double2 *__restrict__ in, S *__restrict__ ou
             double2 w = in[((long)j * V + site) * 12 + k];
             v = {w.x, w.y};
         }
-        stc<double>(o, (long)k * Vp + site, v);
+        stc<double>(o, cpos<S>(k, site, Vp), v);
     }
 }
 
@@ -41,12 +41,12 @@ __global__ void k_unpack_spinor(const S *__restrict__ in, double2 *__restrict__ 
     const S *p = in + (long)s * fstride;
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-        cx<double> v = ldc<double>(p, (long)k * Vp + site);
+        cx<double> v = ldc<double>(p, cpos<S>(k, site, Vp));
         out[((long)j * V + site) * 12 + k] = make_double2(v.x, v.y);
     }
 }
 
-// canonical [4][V][3][3]  ->  planes [4][9][Vp]
+// canonical [4][V][3][3]  ->  internal link layout
 template <class S>
 __global__ void k_pack_links(const double2 *__restrict__ in, S *__restrict__ out, int V, int Vp)
 {
@@ -60,7 +60,7 @@ __global__ void k_pack_links(const double2 *__restrict__ in, S *__restrict__ out
             double2 w = in[((long)mu * V + site) * 9 + k];
             v = {w.x, w.y};
         }
-        stc<double>(out, (long)(mu * 9 + k) * Vp + site, v);
+        stc<double>(out, lpos<S>(mu, k, site, Vp), v);
     }
 }
 
@@ -93,18 +93,26 @@ __global__ __launch_bounds__(256) void k_lincomb(LcArgs<SI, SO> a)
     const long ne = 12L * a.Vp;
     const long half = 6L * a.Vp;
     double nrm = 0.0;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < ne; e += (long)gridDim.x * blockDim.x) {
+    auto elem = [&](long ei, long eo, bool lower) {
         cx<double> v = {0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
             if (t < a.nin) {
-                cx<double> x = ldc<double>(a.in[t] + (long)s * a.istride[t], e);
-                if (((a.g5mask >> t) & 1) && e >= half) x = {-x.x, -x.y};
+                cx<double> x = ldc<double>(a.in[t] + (long)s * a.istride[t], ei);
+                if (((a.g5mask >> t) & 1) && lower) x = {-x.x, -x.y};
                 cfma(v, cf[t], x);
             }
         }
-        stc<double>(a.out + (long)s * a.ostride, e, v);
+        stc<double>(a.out + (long)s * a.ostride, eo, v);
         if (a.red) nrm += v.x * v.x + v.y * v.y;
+    };
+    const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x, nth = (long)gridDim.x * blockDim.x;
+    if constexpr (Pair<SI>::E == Pair<SO>::E) {
+        for (long e = tid; e < ne; e += nth) elem(e, e, e >= half);
+    } else {
+        // layouts differ: walk pair-planes, in which both name the same numbers
+        for (int p = 0; p < 6; ++p)
+            for (long r = tid; r < 2L * a.Vp; r += nth) elem(ppos<SI>(p, r, a.Vp), ppos<SO>(p, r, a.Vp), p >= 3);
     }
     if (a.red) {
         __shared__ double sh[256];
@@ -130,10 +138,17 @@ __global__ __launch_bounds__(256) void k_dot(const SA *__restrict__ a, long astr
     const int s = slots ? slots[j] : j;
     const long ne = 12L * Vp, half = 6L * Vp;
     cx<double> acc = {0.0, 0.0};
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < ne; e += (long)gridDim.x * blockDim.x) {
-        cx<double> x = ldc<double>(a + (long)s * astride, e);
-        if (g5a && e >= half) x = {-x.x, -x.y};
-        cfmac(acc, x, ldc<double>(b + (long)s * bstride, e));
+    const long tid = blockIdx.x * (long)blockDim.x + threadIdx.x, nth = (long)gridDim.x * blockDim.x;
+    auto elem = [&](long ea, long eb, bool lower) {
+        cx<double> x = ldc<double>(a + (long)s * astride, ea);
+        if (g5a && lower) x = {-x.x, -x.y};
+        cfmac(acc, x, ldc<double>(b + (long)s * bstride, eb));
+    };
+    if constexpr (Pair<SA>::E == Pair<SB>::E) {
+        for (long e = tid; e < ne; e += nth) elem(e, e, e >= half);
+    } else {
+        for (int p = 0; p < 6; ++p)
+            for (long r = tid; r < 2L * Vp; r += nth) elem(ppos<SA>(p, r, Vp), ppos<SB>(p, r, Vp), p >= 3);
     }
     __shared__ double shr[256], shi[256];
     shr[threadIdx.x] = acc.x;

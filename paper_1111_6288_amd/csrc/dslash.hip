@@ -38,22 +38,151 @@ __device__ __forceinline__ void stp(S *__restrict__ plane, unsigned site, cx<R> 
     stc<R>((S *)((char *)plane + boff), 0u, v);
 }
 
+// Components k = 2p and 2p+1 of one site: a single 16-byte load for the
+// paired FP32 layout, two plane loads otherwise.
+template <class S, class R>
+__device__ __forceinline__ void ldpair(const S *__restrict__ f, int Vp, int p, unsigned site, cx<R> &a, cx<R> &b)
+{
+    if constexpr (Pair<S>::E == 2) {
+        const float4 v = *(const float4 *)((const char *)(f + (size_t)(2 * p) * (unsigned)Vp) + site * 16u);
+        a = cmk((R)v.x, (R)v.y);
+        b = cmk((R)v.z, (R)v.w);
+    } else {
+        a = ldp<S, R>(f + (size_t)(2 * p) * (unsigned)Vp, site);
+        b = ldp<S, R>(f + (size_t)(2 * p + 1) * (unsigned)Vp, site);
+    }
+}
+
+template <class S, class R>
+__device__ __forceinline__ void stpair(S *__restrict__ f, int Vp, int p, unsigned site, cx<R> a, cx<R> b)
+{
+    if constexpr (Pair<S>::E == 2) {
+        *(float4 *)((char *)(f + (size_t)(2 * p) * (unsigned)Vp) + site * 16u) =
+            make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+    } else {
+        stp<S, R>(f + (size_t)(2 * p) * (unsigned)Vp, site, a);
+        stp<S, R>(f + (size_t)(2 * p + 1) * (unsigned)Vp, site, b);
+    }
+}
+
+// Non-temporal variants for operands that are touched once per launch (the
+// epilogue inputs and the output): the loads and stores carry the
+// non-temporal hint so that they do not displace the stencil's neighbour
+// spinors and links from L2.
+typedef float ov_f4 __attribute__((ext_vector_type(4)));
+typedef double ov_d2 __attribute__((ext_vector_type(2)));
+
+template <class S, class R>
+__device__ __forceinline__ cx<R> ldp_nt(const S *__restrict__ plane, unsigned site)
+{
+    const char *p = (const char *)plane + site * (unsigned)sizeof(S);
+    if constexpr (sizeof(S) == 16) {
+        const ov_d2 v = __builtin_nontemporal_load((const ov_d2 *)p);
+        return cmk((R)v.x, (R)v.y);
+    } else if constexpr (sizeof(S) == 4) {
+        const uint32_t v = __builtin_nontemporal_load((const uint32_t *)p);
+        return cmk((R)bf16_lo(v), (R)bf16_hi(v));
+    } else {
+        return ldp<S, R>(plane, site);
+    }
+}
+
+template <class S, class R>
+__device__ __forceinline__ void stp_nt(S *__restrict__ plane, unsigned site, cx<R> v)
+{
+    char *p = (char *)plane + site * (unsigned)sizeof(S);
+    if constexpr (sizeof(S) == 16) {
+        ov_d2 w = {(double)v.x, (double)v.y};
+        __builtin_nontemporal_store(w, (ov_d2 *)p);
+    } else if constexpr (sizeof(S) == 4) {
+        const uint32_t w = f2bf((float)v.x) | (f2bf((float)v.y) << 16);
+        __builtin_nontemporal_store(w, (uint32_t *)p);
+    } else {
+        stp<S, R>(plane, site, v);
+    }
+}
+
+template <class S, class R>
+__device__ __forceinline__ void ldpair_nt(const S *__restrict__ f, int Vp, int p, unsigned site, cx<R> &a, cx<R> &b)
+{
+    if constexpr (Pair<S>::E == 2) {
+        const ov_f4 v = __builtin_nontemporal_load(
+            (const ov_f4 *)((const char *)(f + (size_t)(2 * p) * (unsigned)Vp) + site * 16u));
+        a = cmk((R)v.x, (R)v.y);
+        b = cmk((R)v.z, (R)v.w);
+    } else {
+        a = ldp_nt<S, R>(f + (size_t)(2 * p) * (unsigned)Vp, site);
+        b = ldp_nt<S, R>(f + (size_t)(2 * p + 1) * (unsigned)Vp, site);
+    }
+}
+
+template <class S, class R>
+__device__ __forceinline__ void stpair_nt(S *__restrict__ f, int Vp, int p, unsigned site, cx<R> a, cx<R> b)
+{
+    if constexpr (Pair<S>::E == 2) {
+        const ov_f4 w = {(float)a.x, (float)a.y, (float)b.x, (float)b.y};
+        __builtin_nontemporal_store(w, (ov_f4 *)((char *)(f + (size_t)(2 * p) * (unsigned)Vp) + site * 16u));
+    } else {
+        stp_nt<S, R>(f + (size_t)(2 * p) * (unsigned)Vp, site, a);
+        stp_nt<S, R>(f + (size_t)(2 * p + 1) * (unsigned)Vp, site, b);
+    }
+}
+
+// Link U_mu(s): components 0..7 as pairs, component 8 on its own plane.
 template <class S, class R>
 __device__ __forceinline__ void load_link(const S *__restrict__ U, int mu, int Vp, unsigned s, cx<R> (&u)[3][3])
 {
+    const S *b = U + (size_t)(mu * 9) * (unsigned)Vp;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) u[a][b] = ldp<S, R>(U + (size_t)(mu * 9 + a * 3 + b) * (unsigned)Vp, s);
+    for (int p = 0; p < 4; ++p)
+        ldpair<S, R>(b, Vp, p, s, u[(2 * p) / 3][(2 * p) % 3], u[(2 * p + 1) / 3][(2 * p + 1) % 3]);
+    u[2][2] = ldp<S, R>(b + (size_t)8 * (unsigned)Vp, s);
 }
 
 template <class S, class R>
 __device__ __forceinline__ void load_spinor(const S *__restrict__ x, int Vp, unsigned s, cx<R> (&p)[4][3])
 {
 #pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
+    for (int q = 0; q < 6; ++q)
+        ldpair<S, R>(x, Vp, q, s, p[(2 * q) / 3][(2 * q) % 3], p[(2 * q + 1) / 3][(2 * q + 1) % 3]);
+}
+
+// Output of one site: v_k = a G (diag x_k - acc_k / 2) + c1 e1_k + c2 e2_k + c3 e3_k.
+template <class S, class R, bool HW, bool EPI>
+__device__ __forceinline__ void write_site(const DsArgs<S> &a, size_t off, unsigned site, const cx<R> (&x)[4][3],
+                                           const cx<R> (&acc)[4][3])
+{
+    const int Vp = a.g.Vp;
+    const R diag = (R)a.diag, sc = (R)a.a;
+    const R cc[3] = {(R)a.c1, (R)a.c2, (R)a.c3};
+    const S *ep[3] = {a.e1, a.e2, a.e3};
+    const bool nt = a.stream_hint != 0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) p[sp][c] = ldp<S, R>(x + (size_t)(sp * 3 + c) * (unsigned)Vp, s);
+    for (int q = 0; q < 6; ++q) {
+        cx<R> v[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = 2 * q + h, sp = k / 3, c = k % 3;
+            v[h] = cmk(diag * x[sp][c].x - (R)0.5 * acc[sp][c].x, diag * x[sp][c].y - (R)0.5 * acc[sp][c].y);
+            v[h] = cscale(v[h], (HW && sp >= 2) ? -sc : sc);
+        }
+        if (EPI) {
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                if (!ep[t]) continue;
+                cx<R> e[2];
+                if (nt) ldpair_nt<S, R>(ep[t] + off, Vp, q, site, e[0], e[1]);
+                else ldpair<S, R>(ep[t] + off, Vp, q, site, e[0], e[1]);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    v[h].x = fma(cc[t], e[h].x, v[h].x);
+                    v[h].y = fma(cc[t], e[h].y, v[h].y);
+                }
+            }
+        }
+        if (nt) stpair_nt<S, R>(a.y + off, Vp, q, site, v[0], v[1]);
+        else stpair<S, R>(a.y + off, Vp, q, site, v[0], v[1]);
+    }
 }
 
 // One direction, both hops, for all NR right-hand sides of this thread.
@@ -190,8 +319,8 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
         for (int r = 0; r < NR; ++r) {
             if (!act[r]) continue;
 #pragma unroll
-            for (int k = 0; k < 12; ++k)
-                stp<S, R>(a.y + off[r] + (size_t)k * (unsigned)g.Vp, (unsigned)site, cmk((R)0, (R)0));
+            for (int q = 0; q < 6; ++q)
+                stpair<S, R>(a.y + off[r], g.Vp, q, (unsigned)site, cmk((R)0, (R)0), cmk((R)0, (R)0));
         }
         return;
     }
@@ -222,30 +351,12 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
     hop_dir<2, NR, S, R>(a, site, zc, g.Lz, g.Lxy, off, act, ph, acc);
     hop_dir<3, NR, S, R>(a, site, tc, g.Lt, g.Lxyz, off, act, ph, acc);
 
-    const R diag = (R)a.diag, sc = (R)a.a;
-    const R c1 = (R)a.c1, c2 = (R)a.c2, c3 = (R)a.c3;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         if (!act[r]) continue;
         cx<R> p[4][3];
         load_spinor<S, R>(a.x + off[r], g.Vp, (unsigned)site, p);
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                cx<R> v = cmk(diag * p[sp][c].x - (R)0.5 * acc[r][sp][c].x,
-                              diag * p[sp][c].y - (R)0.5 * acc[r][sp][c].y);
-                R s = (HW && sp >= 2) ? -sc : sc;
-                v = cscale(v, s);
-                const size_t po = off[r] + (size_t)(sp * 3 + c) * (unsigned)g.Vp;
-                const unsigned us = (unsigned)site;
-                if (EPI) {
-                    if (a.e1) { cx<R> e = ldp<S, R>(a.e1 + po, us); v.x = fma(c1, e.x, v.x); v.y = fma(c1, e.y, v.y); }
-                    if (a.e2) { cx<R> e = ldp<S, R>(a.e2 + po, us); v.x = fma(c2, e.x, v.x); v.y = fma(c2, e.y, v.y); }
-                    if (a.e3) { cx<R> e = ldp<S, R>(a.e3 + po, us); v.x = fma(c3, e.x, v.x); v.y = fma(c3, e.y, v.y); }
-                }
-                stp<S, R>(a.y + po, us, v);
-            }
+        write_site<S, R, HW, EPI>(a, off[r], (unsigned)site, p, acc[r]);
     }
 }
 
@@ -255,17 +366,18 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
 // backward time link in registers: the two time neighbours cost no loads and
 // every input spinor is fetched once per chunk.  A wave covers 64 consecutive
 // sites of one (z, t) plane, so x and y neighbours come from lines the wave
-// itself touches in the same step (L1); the 4 waves of a workgroup are 4 RHS
-// on the same sites, so link loads are shared through L1; blocks walk z
+// itself touches in the same step (L1); the W waves of a workgroup (W = 4 or
+// 8) are W RHS on the same sites, so link loads are shared through L1: the
+// links stream from memory once per W right-hand sides.  Blocks walk z
 // fastest within an XCD, so z neighbours are loaded by workgroups running at
 // the same time on the same XCD (L2).
 //
 // Block b: XCD b & 7, local index m = b >> 3 decomposed as
 //   m = z + Lz (ob + nob (tc + ntc rg))
 // with ob the 64-site block of the (x, y) plane, tc the t-chunk and rg the
-// group of 4 RHS.  Needs V % 64 == 0 (no padding); the launcher checks.
-template <class S, bool HW, bool EPI>
-__global__ __launch_bounds__(256) void k_dslash_tm(DsArgs<S> a)
+// group of W RHS.  Needs V % 64 == 0 (no padding); the launcher checks.
+template <class S, bool HW, bool EPI, int W>
+__global__ __launch_bounds__(64 * W) void k_dslash_tm(DsArgs<S> a)
 {
     using R = typename StoreT<S>::real;
     const Geo &g = a.g;
@@ -281,7 +393,7 @@ __global__ __launch_bounds__(256) void k_dslash_tm(DsArgs<S> a)
     m /= nob;
     const int tc = m % ntc;
     const int rg = m / ntc;
-    const int j = rg * 4 + wave;
+    const int j = rg * W + wave;
     const int o = ob * 64 + lane;
     if (j >= a.n || o >= g.Lxy) return;
 
@@ -305,8 +417,6 @@ __global__ __launch_bounds__(256) void k_dslash_tm(DsArgs<S> a)
 
     const size_t offs[1] = {off};
     const bool acts[1] = {true};
-    const R diag = (R)a.diag, sc = (R)a.a;
-    const R c1 = (R)a.c1, c2 = (R)a.c2, c3 = (R)a.c3;
     const R bt = (R)g.bcf[3];
 
     for (int t = t0; t < t1; ++t) {
@@ -374,22 +484,7 @@ __global__ __launch_bounds__(256) void k_dslash_tm(DsArgs<S> a)
             }
         }
 
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                cx<R> v = cmk(diag * pc[sp][c].x - (R)0.5 * acc[0][sp][c].x,
-                              diag * pc[sp][c].y - (R)0.5 * acc[0][sp][c].y);
-                const R sg = (HW && sp >= 2) ? -sc : sc;
-                v = cscale(v, sg);
-                const size_t po = off + (size_t)(sp * 3 + c) * (unsigned)Vp;
-                if (EPI) {
-                    if (a.e1) { cx<R> e = ldp<S, R>(a.e1 + po, (unsigned)site); v.x = fma(c1, e.x, v.x); v.y = fma(c1, e.y, v.y); }
-                    if (a.e2) { cx<R> e = ldp<S, R>(a.e2 + po, (unsigned)site); v.x = fma(c2, e.x, v.x); v.y = fma(c2, e.y, v.y); }
-                    if (a.e3) { cx<R> e = ldp<S, R>(a.e3 + po, (unsigned)site); v.x = fma(c3, e.x, v.x); v.y = fma(c3, e.y, v.y); }
-                }
-                stp<S, R>(a.y + po, (unsigned)site, v);
-            }
+        write_site<S, R, HW, EPI>(a, off, (unsigned)site, pc, acc[0]);
 
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
@@ -405,23 +500,32 @@ __global__ __launch_bounds__(256) void k_dslash_tm(DsArgs<S> a)
     }
 }
 
-template <class S>
-static hipError_t launch_tm(const DsArgs<S> &a, bool hw, bool epi, hipStream_t st)
+template <class S, int W>
+static hipError_t launch_tm_w(const DsArgs<S> &a, bool hw, bool epi, hipStream_t st)
 {
     DsArgs<S> b = a;
     if (b.tchunk <= 0 || b.tchunk > a.g.Lt) b.tchunk = a.g.Lt;
     const int nob = (a.g.Lxy + 63) / 64;
     const int ntc = (a.g.Lt + b.tchunk - 1) / b.tchunk;
-    const long nblk = (long)a.g.Lz * nob * ntc * ((a.n + 3) / 4);
+    const long nblk = (long)a.g.Lz * nob * ntc * ((a.n + W - 1) / W);
     const long padded = (nblk + 7) / 8 * 8;
     if (padded > 0x7fffffffL) return hipErrorInvalidValue;
+    const dim3 blk(64 * W);
     if (epi)
-        hipLaunchKernelGGL((k_dslash_tm<S, true, true>), dim3((unsigned)padded), dim3(256), 0, st, b);
+        hipLaunchKernelGGL((k_dslash_tm<S, true, true, W>), dim3((unsigned)padded), blk, 0, st, b);
     else if (hw)
-        hipLaunchKernelGGL((k_dslash_tm<S, true, false>), dim3((unsigned)padded), dim3(256), 0, st, b);
+        hipLaunchKernelGGL((k_dslash_tm<S, true, false, W>), dim3((unsigned)padded), blk, 0, st, b);
     else
-        hipLaunchKernelGGL((k_dslash_tm<S, false, false>), dim3((unsigned)padded), dim3(256), 0, st, b);
+        hipLaunchKernelGGL((k_dslash_tm<S, false, false, W>), dim3((unsigned)padded), blk, 0, st, b);
     return hipGetLastError();
+}
+
+// block = 64 W threads, W = 8 right-hand sides per workgroup for block 512, else 4.
+template <class S>
+static hipError_t launch_tm(const DsArgs<S> &a, bool hw, bool epi, int block, hipStream_t st)
+{
+    if (block == 512) return launch_tm_w<S, 8>(a, hw, epi, st);
+    return launch_tm_w<S, 4>(a, hw, epi, st);
 }
 
 template <class S, int NR>
@@ -472,8 +576,9 @@ template <class S>
 hipError_t launch_dslash(const DsArgs<S> &a, bool hw, bool epi, int nr, int block, hipStream_t st)
 {
     if (a.n <= 0) return hipSuccess;
-    if (block < 64 || block > 256 || (block & 63)) return hipErrorInvalidValue;
-    if (a.order == 2 && a.g.V % 64 == 0) return launch_tm<S>(a, hw, epi, st);
+    if (block < 64 || block > 512 || (block & 63)) return hipErrorInvalidValue;
+    if (a.order == 2 && a.g.V % 64 == 0) return launch_tm<S>(a, hw, epi, block, st);
+    if (block > 256) block = 256;   // wider workgroups only for the t-marching kernel
     switch (nr) {
     case 1: return launch_nr<S, 1>(a, hw, epi, block, st);
     case 2: return launch_nr<S, 2>(a, hw, epi, block, st);

@@ -3,8 +3,8 @@
 //
 // Internal field layout ("planes"): a spinor field is 12 planes of Vp
 // complex numbers, plane k = 3*spin + colour, site index fastest, so that a
-// wavefront of 64 consecutive sites reads 64 consecutive complex numbers per
-// load.  A batch of fields is a sequence of such fields, `fstride` storage
+// wavefront of 64 consecutive sites reads 64 consecutive elements per load
+// (FP32 fields pair planes 2p and 2p+1 into 16-byte elements; cpos below).  A batch of fields is a sequence of such fields, `fstride` storage
 // elements apart.  Links are 4*9 planes [mu][3*a+b][Vp].  Vp is V rounded up
 // to a multiple of 64.  Invariant: the padding sites V..Vp-1 of every field
 // hold zeros.  Kernels that reduce or combine whole planes (dots, linear
@@ -167,6 +167,51 @@ template <class R>
 __device__ __forceinline__ void stc(uint32_t *p, long i, cx<R> v)
 {
     p[i] = f2bf((float)v.x) | (f2bf((float)v.y) << 16);
+}
+
+// ---------------------------------------------------------------- layouts
+// Position of complex component k (0..11) of site `site` inside a field, in
+// units of one stored complex number.  FP64 and BF16 fields are 12 planes of
+// one complex per site (16-byte and 4-byte lanes).  FP32 fields pair the
+// components: pair-plane p holds (k = 2p, 2p+1) of a site in one 16-byte
+// element, because on gfx950 a load of 8 bytes per lane costs as many
+// address cycles as one of 16 bytes.  Both layouts keep spins 0,1 (k < 6) in
+// the first half of the field, so flat elementwise kernels and gamma5 (negate
+// the second half) work on either.
+//
+// Links: FP64 and BF16 use 36 planes [mu][3a+b][Vp]; FP32 stores, per mu,
+// the pairs (0,1) (2,3) (4,5) (6,7) as four pair-planes followed by a plain
+// plane for component 8, in the same 9 Vp complex numbers per mu.
+template <class S>
+struct Pair {
+    static constexpr int E = 1;
+};
+template <>
+struct Pair<float2> {
+    static constexpr int E = 2;
+};
+
+template <class S>
+__host__ __device__ __forceinline__ long cpos(int k, long site, long Vp)
+{
+    if (Pair<S>::E == 2) return 2 * ((k >> 1) * Vp + site) + (k & 1);
+    return k * Vp + site;
+}
+
+template <class S>
+__host__ __device__ __forceinline__ long lpos(int mu, int k, long site, long Vp)
+{
+    if (Pair<S>::E == 2 && k < 8) return mu * 9 * Vp + 2 * ((k >> 1) * Vp + site) + (k & 1);
+    return (mu * 9 + k) * Vp + site;
+}
+
+// Mixed-layout traversal: pair-plane p (0..5) and offset r (0..2Vp-1) name
+// the same complex number in both layouts; these give its position.
+template <class S>
+__device__ __forceinline__ long ppos(int p, long r, long Vp)
+{
+    if (Pair<S>::E == 2) return 2 * p * Vp + r;
+    return (2 * p + (r & 1)) * Vp + (r >> 1);
 }
 
 // Lattice geometry passed by value to kernels.

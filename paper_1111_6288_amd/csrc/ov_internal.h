@@ -29,6 +29,7 @@ struct DsArgs {
     int tchunk;              // t-chunk length of order 2 (0: whole Lt)
     int blocks_per_cu;       // occupancy cap (0: none), enforced through reserved LDS
     int xcd_remap;           // set by the launcher
+    int stream_hint;         // 1: epilogue inputs and the output bypass cache retention (non-temporal)
 };
 
 template <class S>

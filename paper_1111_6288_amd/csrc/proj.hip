@@ -5,8 +5,9 @@
 //   proj_dot     C[j][i] = sum_k conj(V_i[k]) (G X_j)[k]        (V^dag X)
 //   proj_expand  Y_j[k]  = alpha X_j[k] + sum_i V_i[k] E[j][i]   (X + V E)
 //
-// V is FP64 (planes [l][12][Vp], the spinor layout).  X and Y may be stored in
-// FP64, FP32 or BF16; every product and sum is FP64.  The dot runs split-K:
+// V is FP64 (planes [l][12][Vp], the spinor layout); k runs over V's planes.
+// X and Y may be stored in FP64, FP32 (paired layout: the position of k is
+// mapped) or BF16; every product and sum is FP64.  The dot runs split-K:
 // each workgroup reduces one K-chunk to a partial l x n block, then a fixed-
 // order pass sums the partials (deterministic).  Both use the matrix cores
 // (v_mfma_f64_16x16x4f64) with 16x16 tiles of (vector, RHS).
@@ -66,13 +67,22 @@ __global__ __launch_bounds__(256) void k_proj_dot_mfma(const double2 *__restrict
         xp[t] = X + (long)s * xstride;
     }
 
+    // (plane, site) of kb, advanced with it: kb and Vp are multiples of 4, so
+    // kb + kq stays in the plane of kb
+    long pl = k0 / Vp, st = k0 - pl * Vp;
     for (long kb = k0; kb < k1; kb += 4) {
         const long k = kb + kq;
         const bool kin = k < k1;
+        const long xk = cpos<S>((int)pl, st + kq, Vp);
+        st += 4;
+        if (st >= Vp) {
+            st -= Vp;
+            ++pl;
+        }
         double xr[NT], xi[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            cx<double> x = (kin && xok[t]) ? ldc<double>(xp[t], k) : cx<double>{0.0, 0.0};
+            cx<double> x = (kin && xok[t]) ? ldc<double>(xp[t], xk) : cx<double>{0.0, 0.0};
             if (g5x && k >= half) x = {-x.x, -x.y};
             xr[t] = x.x;
             xi[t] = x.y;
@@ -138,6 +148,9 @@ __global__ __launch_bounds__(256) void k_proj_expand_mfma(const double2 *__restr
     if (kbase >= K) return;
     const long kk = kbase + col;          // B column handled by this lane
     const bool kok = kk < K;
+    // the 16 columns of a wave lie in one plane (Vp is a multiple of 16)
+    const long pl = kbase / Vp, st = kk - pl * Vp;
+    const long xk = cpos<SX>((int)pl, st, Vp), yk = cpos<SY>((int)pl, st, Vp);
 
     v4d dre[NT], dim[NT];
 #pragma unroll
@@ -168,11 +181,11 @@ __global__ __launch_bounds__(256) void k_proj_expand_mfma(const double2 *__restr
                 const int s = slots ? slots[j] : j;
                 cx<double> y = {beta * dre[t][r], beta * dim[t][r]};
                 if (X) {
-                    cx<double> x = ldc<double>(X + (long)s * xstride, kk);
+                    cx<double> x = ldc<double>(X + (long)s * xstride, xk);
                     y.x = fma(alpha, x.x, y.x);
                     y.y = fma(alpha, x.y, y.y);
                 }
-                stc<double>(Y + (long)s * ystride, kk, y);
+                stc<double>(Y + (long)s * ystride, yk, y);
             }
         }
 }

@@ -77,6 +77,8 @@ def _load():
         "ov_set_graphs": ([vp, i], i),
         "ov_set_site_order": ([vp, i, i], i),
         "ov_set_occupancy": ([vp, i, i], i),
+        "ov_get_launch_config": ([vp, i, i, cp(i)], i),
+        "ov_set_launch_config": ([vp, i, i, cp(i)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -91,7 +93,8 @@ EXPORTED = ("ov_create", "ov_destroy", "ov_set_stream", "ov_last_error", "ov_upl
             "ov_set_sign_params", "ov_upload_eigvecs", "ov_upload_deflation", "ov_dslash", "ov_sign_apply",
             "ov_dov_apply", "ov_deflated_cg", "ov_sign_backward", "ov_prof_enable", "ov_prof_query",
             "ov_set_tuning", "ov_get_tuning", "ov_autotune", "ov_memory_used", "ov_set_graphs",
-            "ov_set_site_order", "ov_set_occupancy")
+            "ov_set_site_order", "ov_set_occupancy", "ov_get_launch_config",
+            "ov_set_launch_config")
 
 
 def _ints(v):
@@ -266,6 +269,25 @@ class Context:
 
     def set_occupancy(self, prec, blocks_per_cu):
         return self._chk(lib.ov_set_occupancy(self._h, PREC[prec], int(blocks_per_cu)))
+
+    _KIND = {"dslash": 0, "clenshaw": 1}
+    _CFG = ("rhs_per_thread", "block", "site_order", "blocks_per_cu", "stream_hint")
+
+    def get_launch_config(self, prec, kind="dslash"):
+        """Launch shape of the plain ("dslash") or fused-epilogue ("clenshaw") launches of prec."""
+        cfg = (C.c_int * 5)()
+        self._chk(lib.ov_get_launch_config(self._h, PREC[prec], self._KIND[kind], cfg))
+        return dict(zip(self._CFG, list(cfg)))
+
+    def set_launch_config(self, prec, kind, **cfg):
+        """Set fields of one kind's launch shape; fields not given keep their value."""
+        cur = self.get_launch_config(prec, kind)
+        for k, v in cfg.items():
+            if k not in cur:
+                raise KeyError(k)
+            cur[k] = int(v)
+        arr = (C.c_int * 5)(*[cur[k] for k in self._CFG])
+        return self._chk(lib.ov_set_launch_config(self._h, PREC[prec], self._KIND[kind], arr))
 
     def get_tuning(self, prec):
         a, b = C.c_int(), C.c_int()

@@ -107,17 +107,21 @@ def test_dslash_zslab_site_order(nr):
 @pytest.mark.parametrize("L,bc", [((4, 4, 4, 4), (0, 0, 0, 1)), ((4, 6, 8, 6), (2, 0, 0, 2)),
                                   ((8, 8, 8, 16), (1, 2, 0, 0))])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-14), ("fp32", 2e-6), ("bf16", 2e-2)])
-def test_dslash_tmarch_order(L, bc, prec, tol):
-    """Site order 2 (threads march along t with the time neighbours in registers)."""
+@pytest.mark.parametrize("block", [256, 512])
+def test_dslash_tmarch_order(L, bc, prec, tol, block):
+    """Site order 2 (threads march along t with the time neighbours in registers),
+    4 or 8 right-hand sides per workgroup; 11 RHS leave a partial group."""
     U = synth.su3_links(L, 0.5, 23)
     q, eta = (2 / 3, -1 / 3, 2 / 3), (0.0, 0.31, -0.12)
     ctx = make_ctx(L, bc, U, q, eta)
     ctx.set_site_order(prec, 2)
-    x = synth.gaussian_spinors(L, 7, 5)
-    fields = [j % 3 for j in range(7)]
+    ctx.set_tuning(prec, 1, block)
+    nrhs = 11
+    x = synth.gaussian_spinors(L, nrhs, 5)
+    fields = [j % 3 for j in range(nrhs)]
     for op, opc in (("HW", 1), ("DW", 0)):
         y = _np(ctx.dslash(_t(x), fields, op=op, prec=prec))
-        for j in range(7):
+        for j in range(nrhs):
             lat = api.Lattice(L, bc, MW, U, q[fields[j]] * eta[fields[j]])
             assert _rel(y[j], api.dslash(lat, x[j], opc)) < tol, (op, j)
 
@@ -135,11 +139,59 @@ def test_sign_with_tmarch_order():
     ctx.upload_eigvecs(0, _t(Vs), lam)
     x = synth.gaussian_spinors(L, 5, 3)
     ref = api.sign(api.Lattice(L, bc, MW, U, 2 / 3 * 1e-3), api.SignParams(n, eps, 6.5, Vs, lam), x[:2])
-    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5)):
+    for prec, tol, block in (("fp64", 1e-12, 256), ("fp32", 2e-5, 256), ("fp32", 2e-5, 512)):
         ctx.set_site_order(prec, 2)
+        ctx.set_tuning(prec, 1, block)
         y = _np(ctx.sign_apply(_t(x), [0] * 5, prec=prec))
         for j in range(2):
-            assert _rel(y[j], ref[j]) < tol
+            assert _rel(y[j], ref[j]) < tol, (prec, block)
+
+
+@pytest.mark.parametrize("order,block,nr", [(0, 128, 2), (1, 64, 1), (2, 256, 1), (2, 512, 1)])
+def test_stream_hint_and_per_kind_shapes(order, block, nr):
+    """Non-temporal epilogue/output accesses and separate plain / fused launch shapes give
+    the oracle's dslash and sign (the hint changes cache policy only)."""
+    L, bc = (8, 8, 8, 16), (2, 0, 0, 2)
+    U = synth.su3_links(L, 0.3, 41)
+    ctx = make_ctx(L, bc, U, (2 / 3, -1 / 3), (1e-3, 0.2))
+    n = 40
+    eps = 0.5 / n ** 2
+    ctx.set_sign_params(n, eps, 6.5)
+    x = synth.gaussian_spinors(L, 9, 8)
+    f = [j % 2 for j in range(9)]
+    for prec, dtol, stol in (("fp64", 1e-14, 1e-12), ("fp32", 2e-6, 2e-5), ("bf16", 2e-2, 3e-2)):
+        if prec == "fp64" and block == 512:
+            continue
+        # plain launches in one shape, fused launches in another, both with the hint
+        ctx.set_launch_config(prec, "dslash", rhs_per_thread=nr, block=block, site_order=order,
+                              blocks_per_cu=0, stream_hint=1)
+        ctx.set_launch_config(prec, "clenshaw", rhs_per_thread=2, block=128, site_order=(order + 1) % 3,
+                              blocks_per_cu=2, stream_hint=1)
+        got = ctx.get_launch_config(prec, "dslash")
+        assert got == dict(rhs_per_thread=nr, block=block, site_order=order, blocks_per_cu=0, stream_hint=1)
+        y = _np(ctx.dslash(_t(x), f, prec=prec))
+        for j in (0, 1, 8):
+            lat = api.Lattice(L, bc, MW, U, (2 / 3 * 1e-3, -1 / 3 * 0.2)[f[j]])
+            assert _rel(y[j], api.dslash(lat, x[j], 1)) < dtol, (prec, j)
+        if prec == "bf16":
+            continue
+        s = _np(ctx.sign_apply(_t(x[:3]), f[:3], prec=prec))
+        for j in range(2):
+            lat = api.Lattice(L, bc, MW, U, (2 / 3 * 1e-3, -1 / 3 * 0.2)[f[j]])
+            ref = api.sign(lat, api.SignParams(n, eps, 6.5), x[j:j + 1])[0]
+            assert _rel(s[j], ref) < stol, (prec, j)
+
+
+def test_launch_config_rejects_bad_values():
+    L, bc = (4, 4, 4, 4), (0, 0, 0, 1)
+    ctx = make_ctx(L, bc, synth.su3_links(L, 0.3, 1))
+    ov = _ov()
+    good = ctx.get_launch_config("fp32", "clenshaw")
+    for bad in (dict(rhs_per_thread=3), dict(block=96), dict(site_order=3), dict(blocks_per_cu=-1),
+                dict(stream_hint=2)):
+        with pytest.raises(ov.OvError):
+            ctx.set_launch_config("fp32", "clenshaw", **bad)
+        assert ctx.get_launch_config("fp32", "clenshaw") == good
 
 
 def test_dslash_deterministic_and_batch_equals_single():
