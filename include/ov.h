@@ -242,13 +242,17 @@ int ov_set_occupancy(ov_ctx *ctx, int prec, int blocks_per_cu);
 /* Launch shape of precision prec for kind 0 (plain H_w / D_w launches) or
  * kind 1 (launches with the fused Clenshaw epilogue), which ov_autotune tunes
  * separately; the three setters above set both kinds.  cfg is
- * {rhs_per_thread, block, site_order, blocks_per_cu, stream_hint}, each with
- * the meaning and range given above; stream_hint 1 marks the operands a
- * launch touches once (epilogue inputs, output) non-temporal so that they do
- * not displace stencil neighbours from L2.  Set: OV_EINVAL on a value out of
- * range (nothing changed). */
-int ov_get_launch_config(ov_ctx *ctx, int prec, int kind, int cfg[5]);
-int ov_set_launch_config(ov_ctx *ctx, int prec, int kind, const int cfg[5]);
+ * {rhs_per_thread, block, site_order, blocks_per_cu, stream_hint, rhs_split},
+ * the first four with the meaning and range given above.  stream_hint 1
+ * marks the operands a launch touches once (epilogue inputs, output)
+ * non-temporal so that they do not displace stencil neighbours from L2.
+ * rhs_split Q in {1, 2, 4} (Q > 1 only with rhs_per_thread <= 2 and site
+ * orders 0, 1) splits each wavefront into Q parts that cover the same 64/Q
+ * sites for Q groups of right-hand sides, so each link is fetched once per
+ * Q * rhs_per_thread RHS.  Set: OV_EINVAL on a value out of range (nothing
+ * changed). */
+int ov_get_launch_config(ov_ctx *ctx, int prec, int kind, int cfg[6]);
+int ov_set_launch_config(ov_ctx *ctx, int prec, int kind, const int cfg[6]);
 int ov_autotune(ov_ctx *ctx, int prec, int nrhs, const char *cache_path);
 
 /*

@@ -90,7 +90,7 @@ struct ov_ctx {
 
     // dslash launch shape per precision and kind (0: plain, 1: fused Clenshaw epilogue)
     struct Launch {
-        int nr = 2, block = 128, order = 0, cap = 0, stream_hint = 0;
+        int nr = 2, block = 128, order = 0, cap = 0, stream_hint = 0, split = 1;
     };
     Launch tune[3][2];
 
@@ -419,10 +419,11 @@ int dslash_launch(ov_ctx *c, const Batch &b, const int *fgroup, const S *x, S *y
         int nch = (int)std::max(1L, std::min((long)c->g.Lt / 4, (4096 + per_chunk - 1) / per_chunk));
         d.tchunk = (c->g.Lt + nch - 1) / nch;
     }
-    int nr = tu.nr;
+    int nr = tu.nr, split = tu.split;
+    while (split > 1 && (split / 2) * nr >= b.n) split /= 2;
     while (nr > 1 && nr / 2 >= b.n) nr /= 2;
     int pi = prof_begin(c);
-    HIPCHK(launch_dslash<S>(d, hw || epi, epi, nr, tu.block, c->stream));
+    HIPCHK(launch_dslash<S>(d, hw || epi, epi, nr, tu.block, split, c->stream));
     const double sb = sizeof(S);
     const int nex = (e1 ? 1 : 0) + (e2 ? 1 : 0) + (e3 ? 1 : 0);
     prof_end(c, pi, epi ? PC_CLENSHAW : PC_DSLASH,
@@ -1146,6 +1147,7 @@ int ov_set_tuning(ov_ctx *c, int prec, int rhs_per_thread, int block)
     for (auto &tu : c->tune[prec]) {
         tu.nr = rhs_per_thread;
         tu.block = block;
+        if (rhs_per_thread > 2) tu.split = 1;
     }
     return OV_OK;
 }
@@ -1182,6 +1184,7 @@ int ov_get_launch_config(ov_ctx *c, int prec, int kind, int *cfg)
     cfg[2] = tu.order;
     cfg[3] = tu.cap;
     cfg[4] = tu.stream_hint;
+    cfg[5] = tu.split;
     return OV_OK;
 }
 
@@ -1191,13 +1194,15 @@ int ov_set_launch_config(ov_ctx *c, int prec, int kind, const int *cfg)
     CHK(check_prec(c, prec));
     if (kind != 0 && kind != 1) return fail(c, OV_EINVAL, "kind must be 0 (plain) or 1 (fused epilogue)");
     if (!cfg) return fail(c, OV_EINVAL, "cfg is NULL");
-    const int nr = cfg[0], bl = cfg[1], od = cfg[2], cp = cfg[3], sh = cfg[4];
+    const int nr = cfg[0], bl = cfg[1], od = cfg[2], cp = cfg[3], sh = cfg[4], sp = cfg[5];
     if (nr != 1 && nr != 2 && nr != 4 && nr != 8) return fail(c, OV_EINVAL, "rhs_per_thread must be 1, 2, 4 or 8");
     if (bl != 64 && bl != 128 && bl != 192 && bl != 256 && bl != 512)
         return fail(c, OV_EINVAL, "block must be 64, 128, 192, 256 or 512");
     if (od < 0 || od > 2) return fail(c, OV_EINVAL, "site order must be 0, 1 or 2");
     if (cp < 0 || cp > 32) return fail(c, OV_EINVAL, "blocks_per_cu outside [0, 32]");
     if (sh != 0 && sh != 1) return fail(c, OV_EINVAL, "stream_hint must be 0 or 1");
+    if (sp != 1 && sp != 2 && sp != 4) return fail(c, OV_EINVAL, "rhs_split must be 1, 2 or 4");
+    if (sp > 1 && nr > 2) return fail(c, OV_EINVAL, "rhs_split > 1 needs rhs_per_thread <= 2");
     invalidate_graphs(c);
     auto &tu = c->tune[prec][kind];
     tu.nr = nr;
@@ -1205,6 +1210,7 @@ int ov_set_launch_config(ov_ctx *c, int prec, int kind, const int *cfg)
     tu.order = od;
     tu.cap = cp;
     tu.stream_hint = sh;
+    tu.split = sp;
     return OV_OK;
 }
 
@@ -1776,7 +1782,8 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e9));
         const int nrs[4] = {1, 2, 4, 8}, blks[4] = {64, 128, 256, 512};
-        const int caps[3] = {0, 2, 4};
+        const int caps[3] = {0, 2, 4}, splits[3] = {1, 2, 4};
+        const int reps = 3;
         const bool was = c->prof_on;
         c->prof_on = false;
         const bool slab_ok = c->g.Lz % 8 == 0 && c->g.V % 64 == 0;
@@ -1794,7 +1801,10 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
             for (int sh = 0; sh < 2 && rc == OV_OK; ++sh)
             for (int od = 0; od < 3 && rc == OV_OK; ++od)
             for (int cp : caps)
+            for (int sp : splits)
             for (int nr : nrs) {
+                if (sp > 1 && (nr > 2 || od == 2)) continue;
+                if (sp > 1 && (sp / 2) * nr >= nrhs) continue;
                 if (od == 1 && !slab_ok) continue;
                 if (od == 2 && (c->g.V % 64 != 0 || nr != 1 || cp != 0)) continue;   // t-marching: one shape
                 if (nr > 1 && nr / 2 >= nrhs) continue;
@@ -1808,9 +1818,9 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
                     tu.order = od;
                     tu.cap = cp;
                     tu.stream_hint = sh;
-                    for (int rep = 0; rep < 2 && rc == OV_OK; ++rep) rc = launch();
+                    tu.split = sp;
+                    if (rc == OV_OK) rc = launch();
                     if (rc == OV_OK && hipEventRecord(e0, c->stream) != hipSuccess) rc = OV_EHIP;
-                    const int reps = 5;
                     for (int rep = 0; rep < reps && rc == OV_OK; ++rep) rc = launch();
                     if (rc == OV_OK && hipEventRecord(e9, c->stream) != hipSuccess) rc = OV_EHIP;
                     if (rc == OV_OK && hipEventSynchronize(e9) != hipSuccess) rc = OV_EHIP;
@@ -1824,7 +1834,7 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
                 }
             }
             tu = rc == OV_OK ? bestc : keep;
-            best_ms[kind] = best / 5.0f;
+            best_ms[kind] = best / (float)reps;
         }
         c->prof_on = was;
         invalidate_graphs(c);
@@ -1839,9 +1849,10 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
                     std::fprintf(fp,
                                  "{\"arch\": \"gfx950\", \"L\": [%d, %d, %d, %d], \"prec\": %d, \"nrhs\": %d, "
                                  "\"kind\": \"%s\", \"rhs_per_thread\": %d, \"block\": %d, \"site_order\": %d, "
-                                 "\"blocks_per_cu\": %d, \"stream_hint\": %d, \"ms_per_launch\": %.6f}\n",
+                                 "\"blocks_per_cu\": %d, \"stream_hint\": %d, \"rhs_split\": %d, "
+                                 "\"ms_per_launch\": %.6f}\n",
                                  c->L[0], c->L[1], c->L[2], c->L[3], prec, nrhs, kind ? "clenshaw" : "dslash",
-                                 tu.nr, tu.block, tu.order, tu.cap, tu.stream_hint, best_ms[kind]);
+                                 tu.nr, tu.block, tu.order, tu.cap, tu.stream_hint, tu.split, best_ms[kind]);
                 }
                 std::fclose(fp);
             }

@@ -271,17 +271,25 @@ __device__ __forceinline__ int xcd_block(int b, int nblk)
     return (b & 7) * per + (b >> 3);
 }
 
-// Site of this thread.  order 0: blocks walk the sites in canonical order,
-// each XCD taking a contiguous run (t-chunks).  order 1: XCD x owns the
-// z-slab [x Lz/8, (x+1) Lz/8) and walks it plane by plane, (z, t) planes of
-// Lx*Ly sites in t-major order, so the cross-section an XCD sweeps is 1/8 of
-// a time slice and t-neighbours are re-read soon after their first use.
-// order 1 needs Lz % 8 == 0 and V % 64 == 0 (no padding); the launcher checks.
+// Site of this thread.  A wave is split into Q sub-waves of 64/Q lanes that
+// cover the same 64/Q consecutive sites for Q different groups of
+// right-hand sides, so a workgroup of B threads covers B/Q sites.  order 0:
+// blocks walk the sites in canonical order, each XCD taking a contiguous run
+// (t-chunks).  order 1: XCD x owns the z-slab [x Lz/8, (x+1) Lz/8) and walks
+// it plane by plane, (z, t) planes of Lx*Ly sites in t-major order, so the
+// cross-section an XCD sweeps is 1/8 of a time slice and t-neighbours are
+// re-read soon after their first use.  order 1 needs Lz % 8 == 0 and
+// V % 64 == 0 (no padding); the launcher checks.
+template <int Q>
 __device__ __forceinline__ int dslash_site(const Geo &g, int order, int xcd_remap)
 {
+    constexpr int SL = 64 / Q;   // sites per wave
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int spb = (int)(blockDim.x >> 6) * SL;
+    const int tb = wave * SL + (lane & (SL - 1));
     if (order == 1) {
         const int xcd = blockIdx.x & 7;
-        const int u = (blockIdx.x >> 3) * blockDim.x + threadIdx.x;
+        const int u = (blockIdx.x >> 3) * spb + tb;
         const int nz = g.Lz >> 3;
         const int q = u / g.Lxy, o = u - q * g.Lxy;
         if (q >= nz * g.Lt) return g.Vp;   // beyond the slab: no work
@@ -289,17 +297,21 @@ __device__ __forceinline__ int dslash_site(const Geo &g, int order, int xcd_rema
         return o + g.Lxy * (xcd * nz + zl + g.Lz * t);
     }
     const int blk = xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
-    return blk * blockDim.x + threadIdx.x;
+    return blk * spb + tb;
 }
 
-template <class S, int NR, bool HW, bool EPI>
+// Q > 1: the Q sub-waves load the same link addresses in one instruction, so
+// a link line is fetched once for Q NR right-hand sides while every lane keeps
+// the registers of NR.
+template <class S, int NR, int Q, bool HW, bool EPI>
 __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
 {
     using R = typename StoreT<S>::real;
     const Geo &g = a.g;
-    const int site = dslash_site(g, a.order, a.xcd_remap);
+    const int site = dslash_site<Q>(g, a.order, a.xcd_remap);
     if (site >= g.Vp) return;
-    const int j0 = blockIdx.y * NR;
+    const int sub = (int)(threadIdx.x & 63) / (64 / Q);
+    const int j0 = (blockIdx.y * Q + sub) * NR;
 
     size_t off[NR];
     bool act[NR];
@@ -308,11 +320,13 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
     for (int r = 0; r < NR; ++r) {
         const int j = j0 + r;
         act[r] = j < a.n;
-        const int jj = act[r] ? j : j0;
-        // the storage index depends on blockIdx.y only: make the compiler see it as uniform
-        const int s = __builtin_amdgcn_readfirstlane(a.slots ? a.slots[jj] : jj);
+        const int jj = act[r] ? j : 0;
+        int s = a.slots ? a.slots[jj] : jj;
+        if (Q == 1) s = __builtin_amdgcn_readfirstlane(s);   // uniform: depends on blockIdx.y only
         off[r] = (size_t)s * (size_t)a.fstride;
-        grp[r] = __builtin_amdgcn_readfirstlane(a.fgroup ? a.fgroup[s] : 0);
+        int gr = a.fgroup ? a.fgroup[s] : 0;
+        if (Q == 1) gr = __builtin_amdgcn_readfirstlane(gr);
+        grp[r] = gr;
     }
     if (site >= g.V) {   // padding sites hold zeros in every field
 #pragma unroll
@@ -528,7 +542,7 @@ static hipError_t launch_tm(const DsArgs<S> &a, bool hw, bool epi, int block, hi
     return launch_tm_w<S, 4>(a, hw, epi, st);
 }
 
-template <class S, int NR>
+template <class S, int NR, int Q>
 static hipError_t launch_nr(const DsArgs<S> &a, bool hw, bool epi, int block, hipStream_t st)
 {
     // Occupancy cap: reserving LDS the kernel does not use limits the number of
@@ -536,60 +550,69 @@ static hipError_t launch_nr(const DsArgs<S> &a, bool hw, bool epi, int block, hi
     // narrows the window of sites in flight so that stencil neighbours are
     // re-read while still in L2.
     const size_t lds = a.blocks_per_cu > 0 ? (size_t)(160 * 1024) / (size_t)a.blocks_per_cu - 256 : 0;
-    int nbx = (a.g.V + block - 1) / block;
+    const int spb = block / Q;   // sites per workgroup
+    // cover every padded site: the padding [V, Vp) is rewritten with zeros
+    int nbx = (a.g.Vp + spb - 1) / spb;
     DsArgs<S> b = a;
     b.xcd_remap = 0;
     if (b.order == 1 && (a.g.Lz % 8 != 0 || a.g.V % 64 != 0)) b.order = 0;
     if (b.order == 1) {
         const int per_xcd = (a.g.Lz / 8) * a.g.Lt * a.g.Lxy;
-        nbx = 8 * ((per_xcd + block - 1) / block);
+        nbx = 8 * ((per_xcd + spb - 1) / spb);
     } else if (nbx >= 64) {   // pad to a multiple of 8 for the XCD remap
         nbx = (nbx + 7) & ~7;
         b.xcd_remap = 1;
     }
-    dim3 grid(nbx, (a.n + NR - 1) / NR);
+    dim3 grid(nbx, (a.n + NR * Q - 1) / (NR * Q));
     if (lds > 0) {   // allow more than the default 64 KiB of dynamic LDS (once per kernel)
         static bool raised[3] = {false, false, false};
         const int ki = epi ? 0 : (hw ? 1 : 2);
         if (!raised[ki]) {
             hipError_t e;
-            if (epi) e = hipFuncSetAttribute((const void *)k_dslash<S, NR, true, true>,
+            if (epi) e = hipFuncSetAttribute((const void *)k_dslash<S, NR, Q, true, true>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            else if (hw) e = hipFuncSetAttribute((const void *)k_dslash<S, NR, true, false>,
+            else if (hw) e = hipFuncSetAttribute((const void *)k_dslash<S, NR, Q, true, false>,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            else e = hipFuncSetAttribute((const void *)k_dslash<S, NR, false, false>,
+            else e = hipFuncSetAttribute((const void *)k_dslash<S, NR, Q, false, false>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             if (e != hipSuccess) return e;
             raised[ki] = true;
         }
     }
     if (epi)
-        hipLaunchKernelGGL((k_dslash<S, NR, true, true>), grid, dim3(block), lds, st, b);
+        hipLaunchKernelGGL((k_dslash<S, NR, Q, true, true>), grid, dim3(block), lds, st, b);
     else if (hw)
-        hipLaunchKernelGGL((k_dslash<S, NR, true, false>), grid, dim3(block), lds, st, b);
+        hipLaunchKernelGGL((k_dslash<S, NR, Q, true, false>), grid, dim3(block), lds, st, b);
     else
-        hipLaunchKernelGGL((k_dslash<S, NR, false, false>), grid, dim3(block), lds, st, b);
+        hipLaunchKernelGGL((k_dslash<S, NR, Q, false, false>), grid, dim3(block), lds, st, b);
     return hipGetLastError();
 }
 
+// split = Q sub-waves per wave (1, 2, 4; Q > 1 with NR <= 2 only).
 template <class S>
-hipError_t launch_dslash(const DsArgs<S> &a, bool hw, bool epi, int nr, int block, hipStream_t st)
+hipError_t launch_dslash(const DsArgs<S> &a, bool hw, bool epi, int nr, int block, int split, hipStream_t st)
 {
     if (a.n <= 0) return hipSuccess;
     if (block < 64 || block > 512 || (block & 63)) return hipErrorInvalidValue;
     if (a.order == 2 && a.g.V % 64 == 0) return launch_tm<S>(a, hw, epi, block, st);
     if (block > 256) block = 256;   // wider workgroups only for the t-marching kernel
+    if (split == 2 || split == 4) {
+        if (nr == 1) return split == 2 ? launch_nr<S, 1, 2>(a, hw, epi, block, st) : launch_nr<S, 1, 4>(a, hw, epi, block, st);
+        if (nr == 2) return split == 2 ? launch_nr<S, 2, 2>(a, hw, epi, block, st) : launch_nr<S, 2, 4>(a, hw, epi, block, st);
+        return hipErrorInvalidValue;
+    }
+    if (split != 1) return hipErrorInvalidValue;
     switch (nr) {
-    case 1: return launch_nr<S, 1>(a, hw, epi, block, st);
-    case 2: return launch_nr<S, 2>(a, hw, epi, block, st);
-    case 4: return launch_nr<S, 4>(a, hw, epi, block, st);
-    case 8: return launch_nr<S, 8>(a, hw, epi, block, st);
+    case 1: return launch_nr<S, 1, 1>(a, hw, epi, block, st);
+    case 2: return launch_nr<S, 2, 1>(a, hw, epi, block, st);
+    case 4: return launch_nr<S, 4, 1>(a, hw, epi, block, st);
+    case 8: return launch_nr<S, 8, 1>(a, hw, epi, block, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-template hipError_t launch_dslash<double2>(const DsArgs<double2> &, bool, bool, int, int, hipStream_t);
-template hipError_t launch_dslash<float2>(const DsArgs<float2> &, bool, bool, int, int, hipStream_t);
-template hipError_t launch_dslash<uint32_t>(const DsArgs<uint32_t> &, bool, bool, int, int, hipStream_t);
+template hipError_t launch_dslash<double2>(const DsArgs<double2> &, bool, bool, int, int, int, hipStream_t);
+template hipError_t launch_dslash<float2>(const DsArgs<float2> &, bool, bool, int, int, int, hipStream_t);
+template hipError_t launch_dslash<uint32_t>(const DsArgs<uint32_t> &, bool, bool, int, int, int, hipStream_t);
 
 }  // namespace ov

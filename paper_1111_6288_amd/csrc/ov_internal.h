@@ -33,7 +33,7 @@ struct DsArgs {
 };
 
 template <class S>
-hipError_t launch_dslash(const DsArgs<S> &a, bool hw, bool epi, int nr, int block, hipStream_t st);
+hipError_t launch_dslash(const DsArgs<S> &a, bool hw, bool epi, int nr, int block, int split, hipStream_t st);
 
 // ---------------------------------------------------------------- lincomb
 template <class SI, class SO>

@@ -271,11 +271,11 @@ class Context:
         return self._chk(lib.ov_set_occupancy(self._h, PREC[prec], int(blocks_per_cu)))
 
     _KIND = {"dslash": 0, "clenshaw": 1}
-    _CFG = ("rhs_per_thread", "block", "site_order", "blocks_per_cu", "stream_hint")
+    _CFG = ("rhs_per_thread", "block", "site_order", "blocks_per_cu", "stream_hint", "rhs_split")
 
     def get_launch_config(self, prec, kind="dslash"):
         """Launch shape of the plain ("dslash") or fused-epilogue ("clenshaw") launches of prec."""
-        cfg = (C.c_int * 5)()
+        cfg = (C.c_int * 6)()
         self._chk(lib.ov_get_launch_config(self._h, PREC[prec], self._KIND[kind], cfg))
         return dict(zip(self._CFG, list(cfg)))
 
@@ -286,7 +286,7 @@ class Context:
             if k not in cur:
                 raise KeyError(k)
             cur[k] = int(v)
-        arr = (C.c_int * 5)(*[cur[k] for k in self._CFG])
+        arr = (C.c_int * 6)(*[cur[k] for k in self._CFG])
         return self._chk(lib.ov_set_launch_config(self._h, PREC[prec], self._KIND[kind], arr))
 
     def get_tuning(self, prec):
