@@ -232,8 +232,9 @@ int ov_get_tuning(ov_ctx *ctx, int prec, int *rhs_per_thread, int *block);
  * time slices; 1 = each XCD walks a z-slab plane by plane (needs Lz % 8 == 0
  * and V % 64 == 0); 2 = every thread owns one (x, y, z) site and one RHS and
  * marches along t, keeping the time neighbours in registers (needs
- * V % 64 == 0).  Where a requirement fails, order 0 is used.  ov_autotune
- * searches all three. */
+ * V % 64 == 0); 3 = each XCD walks a t-slab, t fastest (needs Lt % 8 == 0
+ * and V % 64 == 0).  Where a requirement fails, order 0 is used.
+ * ov_autotune searches all four. */
 int ov_set_site_order(ov_ctx *ctx, int prec, int order);
 /* Cap on resident dslash workgroups per CU (0 = no cap).  A small cap keeps
  * the set of sites in flight narrow enough for stencil neighbours to be
@@ -246,10 +247,10 @@ int ov_set_occupancy(ov_ctx *ctx, int prec, int blocks_per_cu);
  * the first four with the meaning and range given above.  stream_hint 1
  * marks the operands a launch touches once (epilogue inputs, output)
  * non-temporal so that they do not displace stencil neighbours from L2.
- * rhs_split Q in {1, 2, 4} (Q > 1 only with rhs_per_thread <= 2 and site
- * orders 0, 1) splits each wavefront into Q parts that cover the same 64/Q
- * sites for Q groups of right-hand sides, so each link is fetched once per
- * Q * rhs_per_thread RHS.  Set: OV_EINVAL on a value out of range (nothing
+ * rhs_split Q in {1, 2, 4, 8} (Q > 1 only with rhs_per_thread <= 2 and
+ * site orders 0, 1; Q = 8 not for BF16 storage) splits each wavefront into Q
+ * parts that cover the same 64/Q sites for Q groups of right-hand sides, so
+ * each link is fetched once per Q * rhs_per_thread RHS.  Set: OV_EINVAL on a value out of range (nothing
  * changed). */
 int ov_get_launch_config(ov_ctx *ctx, int prec, int kind, int cfg[6]);
 int ov_set_launch_config(ov_ctx *ctx, int prec, int kind, const int cfg[6]);

@@ -1156,7 +1156,7 @@ int ov_set_site_order(ov_ctx *c, int prec, int order)
 {
     CHK(check_ctx(c));
     CHK(check_prec(c, prec));
-    if (order < 0 || order > 2) return fail(c, OV_EINVAL, "site order must be 0, 1 or 2");
+    if (order < 0 || order > 3) return fail(c, OV_EINVAL, "site order must be 0, 1, 2 or 3");
     invalidate_graphs(c);
     for (auto &tu : c->tune[prec]) tu.order = order;
     return OV_OK;
@@ -1198,10 +1198,11 @@ int ov_set_launch_config(ov_ctx *c, int prec, int kind, const int *cfg)
     if (nr != 1 && nr != 2 && nr != 4 && nr != 8) return fail(c, OV_EINVAL, "rhs_per_thread must be 1, 2, 4 or 8");
     if (bl != 64 && bl != 128 && bl != 192 && bl != 256 && bl != 512)
         return fail(c, OV_EINVAL, "block must be 64, 128, 192, 256 or 512");
-    if (od < 0 || od > 2) return fail(c, OV_EINVAL, "site order must be 0, 1 or 2");
+    if (od < 0 || od > 3) return fail(c, OV_EINVAL, "site order must be 0, 1, 2 or 3");
     if (cp < 0 || cp > 32) return fail(c, OV_EINVAL, "blocks_per_cu outside [0, 32]");
     if (sh != 0 && sh != 1) return fail(c, OV_EINVAL, "stream_hint must be 0 or 1");
-    if (sp != 1 && sp != 2 && sp != 4) return fail(c, OV_EINVAL, "rhs_split must be 1, 2 or 4");
+    if (sp != 1 && sp != 2 && sp != 4 && sp != 8) return fail(c, OV_EINVAL, "rhs_split must be 1, 2, 4 or 8");
+    if (sp == 8 && prec == OV_BF16) return fail(c, OV_EINVAL, "rhs_split 8 is for FP64 and FP32 storage");
     if (sp > 1 && nr > 2) return fail(c, OV_EINVAL, "rhs_split > 1 needs rhs_per_thread <= 2");
     invalidate_graphs(c);
     auto &tu = c->tune[prec][kind];
@@ -1782,11 +1783,12 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e9));
         const int nrs[4] = {1, 2, 4, 8}, blks[4] = {64, 128, 256, 512};
-        const int caps[3] = {0, 2, 4}, splits[3] = {1, 2, 4};
+        const int caps[3] = {0, 2, 4}, splits[4] = {1, 2, 4, 8};
         const int reps = 3;
         const bool was = c->prof_on;
         c->prof_on = false;
         const bool slab_ok = c->g.Lz % 8 == 0 && c->g.V % 64 == 0;
+        const bool tslab_ok = c->g.Lt % 8 == 0 && c->g.V % 64 == 0;
         float best_ms[2] = {0, 0};
         int rc = OV_OK;
         for (int kind = 0; kind < 2 && rc == OV_OK; ++kind) {
@@ -1799,13 +1801,15 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
             auto bestc = tu;
             float best = 1e30f;
             for (int sh = 0; sh < 2 && rc == OV_OK; ++sh)
-            for (int od = 0; od < 3 && rc == OV_OK; ++od)
+            for (int od = 0; od < 4 && rc == OV_OK; ++od)
             for (int cp : caps)
             for (int sp : splits)
             for (int nr : nrs) {
                 if (sp > 1 && (nr > 2 || od == 2)) continue;
                 if (sp > 1 && (sp / 2) * nr >= nrhs) continue;
+                if (sp == 8 && prec == OV_BF16) continue;
                 if (od == 1 && !slab_ok) continue;
+                if (od == 3 && !tslab_ok) continue;
                 if (od == 2 && (c->g.V % 64 != 0 || nr != 1 || cp != 0)) continue;   // t-marching: one shape
                 if (nr > 1 && nr / 2 >= nrhs) continue;
                 if (prec == OV_FP64 && nr == 8) continue;

@@ -278,8 +278,12 @@ __device__ __forceinline__ int xcd_block(int b, int nblk)
 // (t-chunks).  order 1: XCD x owns the z-slab [x Lz/8, (x+1) Lz/8) and walks
 // it plane by plane, (z, t) planes of Lx*Ly sites in t-major order, so the
 // cross-section an XCD sweeps is 1/8 of a time slice and t-neighbours are
-// re-read soon after their first use.  order 1 needs Lz % 8 == 0 and
-// V % 64 == 0 (no padding); the launcher checks.
+// re-read soon after their first use.  order 3: XCD x owns the t-slab
+// [x Lt/8, (x+1) Lt/8) and walks its (z, t) planes with t fastest, so t
+// neighbours are one plane away and z neighbours Lt/8 planes away; only the
+// two boundary slices of a slab read neighbours another XCD fetched (2/(Lt/8)
+// per site, against 2/(Lz/8) for order 1).  orders 1 and 3 need Lz % 8 == 0
+// (Lt % 8 == 0) and V % 64 == 0 (no padding); the launcher checks.
 template <int Q>
 __device__ __forceinline__ int dslash_site(const Geo &g, int order, int xcd_remap)
 {
@@ -287,6 +291,15 @@ __device__ __forceinline__ int dslash_site(const Geo &g, int order, int xcd_rema
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int spb = (int)(blockDim.x >> 6) * SL;
     const int tb = wave * SL + (lane & (SL - 1));
+    if (order == 3) {
+        const int xcd = blockIdx.x & 7;
+        const int u = (blockIdx.x >> 3) * spb + tb;
+        const int nt = g.Lt >> 3;
+        const int q = u / g.Lxy, o = u - q * g.Lxy;
+        if (q >= nt * g.Lz) return g.Vp;   // beyond the slab: no work
+        const int tl = q % nt, z = q / nt;
+        return o + g.Lxy * (z + g.Lz * (xcd * nt + tl));
+    }
     if (order == 1) {
         const int xcd = blockIdx.x & 7;
         const int u = (blockIdx.x >> 3) * spb + tb;
@@ -556,8 +569,10 @@ static hipError_t launch_nr(const DsArgs<S> &a, bool hw, bool epi, int block, hi
     DsArgs<S> b = a;
     b.xcd_remap = 0;
     if (b.order == 1 && (a.g.Lz % 8 != 0 || a.g.V % 64 != 0)) b.order = 0;
-    if (b.order == 1) {
-        const int per_xcd = (a.g.Lz / 8) * a.g.Lt * a.g.Lxy;
+    if (b.order == 3 && (a.g.Lt % 8 != 0 || a.g.V % 64 != 0)) b.order = 0;
+    if (b.order == 2) b.order = 0;   // t-marching shapes that cannot march use order 0
+    if (b.order == 1 || b.order == 3) {
+        const int per_xcd = a.g.V / 8;
         nbx = 8 * ((per_xcd + spb - 1) / spb);
     } else if (nbx >= 64) {   // pad to a multiple of 8 for the XCD remap
         nbx = (nbx + 7) & ~7;
@@ -588,7 +603,8 @@ static hipError_t launch_nr(const DsArgs<S> &a, bool hw, bool epi, int block, hi
     return hipGetLastError();
 }
 
-// split = Q sub-waves per wave (1, 2, 4; Q > 1 with NR <= 2 only).
+// split = Q sub-waves per wave (1, 2, 4, 8; Q > 1 with NR <= 2 only; Q = 8
+// keeps whole 128-byte lines per sub-wave for 16-byte elements only).
 template <class S>
 hipError_t launch_dslash(const DsArgs<S> &a, bool hw, bool epi, int nr, int block, int split, hipStream_t st)
 {
@@ -600,6 +616,14 @@ hipError_t launch_dslash(const DsArgs<S> &a, bool hw, bool epi, int nr, int bloc
         if (nr == 1) return split == 2 ? launch_nr<S, 1, 2>(a, hw, epi, block, st) : launch_nr<S, 1, 4>(a, hw, epi, block, st);
         if (nr == 2) return split == 2 ? launch_nr<S, 2, 2>(a, hw, epi, block, st) : launch_nr<S, 2, 4>(a, hw, epi, block, st);
         return hipErrorInvalidValue;
+    }
+    if (split == 8) {
+        if constexpr (sizeof(S) == 4) return hipErrorInvalidValue;   // BF16: 32-byte pieces of a line
+        else {
+            if (nr == 1) return launch_nr<S, 1, 8>(a, hw, epi, block, st);
+            if (nr == 2) return launch_nr<S, 2, 8>(a, hw, epi, block, st);
+            return hipErrorInvalidValue;
+        }
     }
     if (split != 1) return hipErrorInvalidValue;
     switch (nr) {

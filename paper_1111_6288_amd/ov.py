@@ -297,3 +297,23 @@ class Context:
     def autotune(self, prec, nrhs, cache_path=None):
         return self._chk(lib.ov_autotune(self._h, PREC[prec], int(nrhs),
                                          cache_path.encode() if cache_path else None))
+
+    def load_tuning(self, path, prec, nrhs):
+        """Apply the launch shapes recorded by autotune (one JSON object per line) for this
+        lattice, precision and batch size; returns the kinds applied (empty if none match)."""
+        import json
+        applied = []
+        try:
+            lines = open(path).read().splitlines()
+        except OSError:
+            return applied
+        for line in lines:
+            if not line.strip():
+                continue
+            e = json.loads(line)
+            if (e.get("arch") != "gfx950" or tuple(e.get("L", ())) != self.L or e.get("prec") != PREC[prec]
+                    or e.get("nrhs") != int(nrhs) or e.get("kind") not in self._KIND):
+                continue
+            self.set_launch_config(prec, e["kind"], **{k: e[k] for k in self._CFG})
+            applied.append(e["kind"])
+        return applied
