@@ -60,7 +60,8 @@ enum {
     OV_ENOCONV = -4,  /* CG reached maxiter; best iterate and report written  */
     OV_ENAN = -5,     /* NaN/Inf detected in an input or a residual           */
     OV_ESTATE = -6,   /* call out of order (e.g. no gauge field uploaded)     */
-    OV_ENORM = -7     /* norm bound below ||H_w|| detected (Clenshaw growth)  */
+    OV_ENORM = -7,    /* norm bound below ||H_w|| detected (Clenshaw growth)  */
+    OV_EBREAKDOWN = -8 /* numerical breakdown (e.g. a Gram matrix not positive) */
 };
 
 enum { OV_FP64 = 0, OV_FP32 = 1, OV_BF16 = 2 };
@@ -189,6 +190,61 @@ typedef struct {
 int ov_deflated_cg(ov_ctx *ctx, int nrhs, const int *field_of_rhs, const double *mass,
                    const void *b_dev, void *x_dev, const ov_cg_opts *opts,
                    ov_cg_rhs_report *report);
+
+/*
+ * Lowest-|lambda| eigenpairs of H_w for field group `field`: the low modes
+ * that the sign function treats exactly (Sec. 2, Fig. 1), which the paper
+ * computes by Arnoldi with Chebyshev acceleration (Sec. 3.1).  Here:
+ * Chebyshev-filtered subspace iteration on a block of k >= l vectors.  Each
+ * pass
+ *   1. filters the block with the degree-m Chebyshev polynomial in H_w^2
+ *      that damps [a, norm^2] (scaled recurrence, normalised at the lowest
+ *      Ritz value of H_w^2; 2m H_w applications per vector, precision
+ *      opts->prec: OV_FP64 or OV_FP32);
+ *   2. orthonormalises it in FP64 (shifted Cholesky QR, then two plain
+ *      Cholesky QR passes; Gram matrices on the matrix cores);
+ *   3. Rayleigh-Ritz with H_w on its span (FP64), Ritz pairs sorted by
+ *      |theta|; residuals r_j = ||H_w x_j - theta_j x_j|| (unit x_j).
+ * It stops when the l lowest satisfy r_j <= tol * norm, or after max_iter
+ * passes.  The first pass uses a = opts->cutoff (in units of H_w^2; <= 0:
+ * norm^2 / 100), later passes the largest Ritz value of H_w^2 in the block.
+ * norm is the bound of ov_set_sign_params (required).
+ *   X0_dev  [k][V][4][3] complex128 start block (read only; e.g. Gaussian).
+ *   V_dev   [l][V][4][3] complex128 eigenvectors out, or NULL.
+ *   lambda  host [l] eigenvalues (ascending |lambda|); resid host [l] or NULL.
+ *   install != 0: the pairs become the group's small space, as by
+ *           ov_upload_eigvecs.
+ * Workspace: 4 FP64 blocks of k fields (+ 4 FP32 blocks for an FP32 filter).
+ * Synchronises.  OV_ENOCONV: not converged (outputs hold the last pass);
+ * OV_EBREAKDOWN: the start block is numerically rank deficient.
+ */
+typedef struct {
+    int l;             /* wanted eigenpairs, 1 <= l <= k                                      */
+    int k;             /* block size, k <= 256 (a few more than l speeds convergence)         */
+    int cheb_order;    /* m, degree of the filter in H_w^2                                     */
+    double cutoff;     /* first-pass lower end a of the damped interval, in units of H_w^2     */
+    int max_iter;      /* passes                                                               */
+    double tol;        /* residual bound relative to the norm bound                            */
+    int prec;          /* filter precision: OV_FP64 or OV_FP32                                 */
+} ov_eig_opts;
+
+typedef struct {
+    int iters;         /* passes run                                                           */
+    long hw_applies;   /* H_w applications on single vectors                                   */
+    double max_resid;  /* max_j r_j over the l wanted pairs                                    */
+} ov_eig_report;
+
+int ov_hw_eigensolve(ov_ctx *ctx, int field, const ov_eig_opts *opts, const void *X0_dev, void *V_dev,
+                     double *lambda, double *resid, int install, ov_eig_report *report);
+
+/*
+ * Host utility (no context, no GPU): eigen-decomposition of a Hermitian
+ * n x n matrix by cyclic Jacobi rotations, as the eigensolver's
+ * Rayleigh-Ritz step uses it.  A: column-major complex (interleaved re, im),
+ * only its Hermitian part is used; w: n ascending eigenvalues; Z:
+ * column-major complex eigenvectors.  Returns 0, or -1 on a bad argument.
+ */
+int ov_dense_heev(int n, const double *A, double *w, double *Z);
 
 /*
  * Adjoint of the sign function for L = Re<g, s(U, eta) x> with the small

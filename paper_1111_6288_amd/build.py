@@ -20,7 +20,7 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libov.so")
 ARCH = os.environ.get("OV_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["dslash.hip", "blas.hip", "proj.hip", "force.hip", "api.hip"]
+SOURCES = ["dslash.hip", "blas.hip", "proj.hip", "force.hip", "api.hip", "dense.cpp"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

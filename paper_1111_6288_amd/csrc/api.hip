@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -23,6 +24,7 @@
 #include <string>
 #include <vector>
 
+#include "dense.h"
 #include "ov.h"
 #include "ov_internal.h"
 
@@ -1866,6 +1868,336 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
     if (prec == OV_FP64) return run(double2{});
     if (prec == OV_FP32) return run(float2{});
     return run(uint32_t{});
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- H_w eigensolver
+namespace {
+
+using cd = std::complex<double>;
+
+// C[j][i] = <V_i, X_j> for nx contiguous fields X (chunks of 48 per launch).
+int block_gram(ov_ctx *c, const double2 *V, int lv, const double2 *X, int nx, double2 *C, double2 *part)
+{
+    const long fe = (long)field_elems(c);
+    for (int j0 = 0; j0 < nx; j0 += 48) {
+        const int nn = std::min(48, nx - j0);
+        int pi = prof_begin(c);
+        HIPCHK(launch_proj_dot<double2>(V, lv, fe, X + (long)j0 * fe, fe, nullptr, nn, c->g.Vp, 0, part,
+                                        C + (long)j0 * lv, c->stream));
+        prof_end(c, pi, PC_PROJ_DOT, (double)fe * (lv * 16.0 + nn * 16.0));
+    }
+    return OV_OK;
+}
+
+// Y_j = sum_i V_i E[j][i] for nx output fields (Y must not alias V).
+int block_rotate(ov_ctx *c, const double2 *V, int lv, const double2 *E, int nx, double2 *Y)
+{
+    const long fe = (long)field_elems(c);
+    for (int j0 = 0; j0 < nx; j0 += 48) {
+        const int nn = std::min(48, nx - j0);
+        int pi = prof_begin(c);
+        HIPCHK((launch_proj_expand<double2, double2>(V, lv, fe, nullptr, fe, 0.0, Y + (long)j0 * fe, fe, nullptr, nn,
+                                                     c->g.Vp, E + (long)j0 * lv, 1.0, c->stream)));
+        prof_end(c, pi, PC_PROJ_EXPAND, (double)fe * (lv * 16.0 + nn * 16.0));
+    }
+    return OV_OK;
+}
+
+// k x k matrix C[j][i] on the device -> column-major host matrix (element (i, j)).
+int fetch_square(ov_ctx *c, const double2 *C, int k, std::vector<cd> &M)
+{
+    std::vector<double2> h((size_t)k * k);
+    HIPCHK(hipMemcpyAsync(h.data(), C, 16ul * k * k, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    M.resize((size_t)k * k);
+    for (size_t e = 0; e < h.size(); ++e) M[e] = cd(h[e].x, h[e].y);
+    for (int j = 0; j < k; ++j)   // Hermitian part
+        for (int i = 0; i < j; ++i) {
+            const cd v = 0.5 * (M[i + (size_t)k * j] + std::conj(M[j + (size_t)k * i]));
+            M[i + (size_t)k * j] = v;
+            M[j + (size_t)k * i] = std::conj(v);
+        }
+    for (int i = 0; i < k; ++i) M[i + (size_t)k * i] = M[i + (size_t)k * i].real();
+    return OV_OK;
+}
+
+int put_square(ov_ctx *c, const std::vector<cd> &M, double2 *E)
+{
+    std::vector<double2> h(M.size());
+    for (size_t e = 0; e < M.size(); ++e) h[e] = make_double2(M[e].real(), M[e].imag());
+    HIPCHK(h2d(c, E, h.data(), 16ul * h.size()));
+    return OV_OK;
+}
+
+// Q = Y R^{-1} with R^H R = Y^dag Y + shift, R upper triangular.
+int cholqr_pass(ov_ctx *c, const double2 *Y, double2 *Q, int k, bool shifted, double2 *G, double2 *E, double2 *part)
+{
+    CHK(block_gram(c, Y, k, Y, k, G, part));
+    std::vector<cd> M;
+    CHK(fetch_square(c, G, k, M));
+    if (shifted) {   // shifted Cholesky QR: the factorisation exists for any numerically full-rank Y
+        double tr = 0;
+        for (int i = 0; i < k; ++i) tr += M[i + (size_t)k * i].real();
+        const double rows = 12.0 * c->g.V;
+        const double s = 11.0 * (rows * k + (double)k * (k + 1)) * 1.1102230246251565e-16 * tr;
+        for (int i = 0; i < k; ++i) M[i + (size_t)k * i] += s;
+    }
+    const int bad = ov::potrf_upper(k, M.data());
+    if (bad) return fail(c, OV_EBREAKDOWN, "eigensolver: Gram matrix not positive definite at pivot %d", bad);
+    ov::trinv_upper(k, M.data());
+    // E[j][i] = Rinv(i, j): the column-major layout of Rinv
+    CHK(put_square(c, M, E));
+    return block_rotate(c, Y, k, E, k, Q);
+}
+
+struct EigBufs {
+    double2 *B[4] = {nullptr, nullptr, nullptr, nullptr};   // FP64 blocks of k fields
+    double2 *G = nullptr, *E = nullptr, *part = nullptr, *coef = nullptr;
+    double *red = nullptr, *r2 = nullptr;
+};
+
+// Scaled Chebyshev filter (Zhou and Saad) in H_w^2: damps the interval
+// [a, bnd], amplifies below a, normalised to 1 at lref < a.  F[0] holds the
+// input; returns the index in F of the output.
+template <class S>
+int cheb_filter(ov_ctx *c, const Batch &b, const int *fg, S *const F[3], S *T, int m, double a, double bnd,
+                double lref, int &iout)
+{
+    const double e = 0.5 * (bnd - a), cc = 0.5 * (bnd + a);
+    double sigma = e / (lref - cc);
+    const double tau = 2.0 / sigma;
+    // F1 = (sigma/e) (H^2 - cc) F0
+    CHK(dslash_launch<S>(c, b, fg, F[0], T, 1.0, true));
+    CHK(dslash_launch<S>(c, b, fg, T, F[1], sigma / e, true, F[0], -(sigma / e) * cc));
+    int i0 = 0, i1 = 1;
+    for (int j = 2; j <= m; ++j) {
+        const double sn = 1.0 / (tau - sigma);
+        const int i2 = 3 - i0 - i1;
+        CHK(dslash_launch<S>(c, b, fg, F[i1], T, 1.0, true));
+        CHK(dslash_launch<S>(c, b, fg, T, F[i2], 2.0 * sn / e, true, F[i1], -2.0 * sn / e * cc, F[i0], -sigma * sn));
+        sigma = sn;
+        i0 = i1;
+        i1 = i2;
+    }
+    iout = (m >= 1) ? i1 : 0;
+    return OV_OK;
+}
+
+int install_small(ov_ctx *c, int field, int l, const double2 *Vplanes, const double *lambda)
+{
+    Small &sm = c->small[field];
+    HIPCHK(hipStreamSynchronize(c->stream));
+    invalidate_graphs(c);
+    dev_free(c, sm.V, 16ul * 12 * c->g.Vp * sm.l);
+    dev_free(c, sm.sgn, 8ul * sm.l);
+    sm = Small();
+    double2 *Vp = nullptr;
+    double *sg = nullptr;
+    CHK(dev_alloc(c, (void **)&Vp, 16ul * 12 * c->g.Vp * l));
+    CHK(dev_alloc(c, (void **)&sg, 8ul * l));
+    std::vector<double> sgn(l);
+    for (int i = 0; i < l; ++i) sgn[i] = lambda[i] >= 0 ? 1.0 : -1.0;
+    HIPCHK(h2d(c, sg, sgn.data(), 8ul * l));
+    HIPCHK(hipMemcpyAsync(Vp, Vplanes, 16ul * 12 * c->g.Vp * l, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    sm.l = l;
+    sm.V = Vp;
+    sm.sgn = sg;
+    return OV_OK;
+}
+
+template <class S>
+int api_eigensolve(ov_ctx *c, int field, const ov_eig_opts &o, const void *X0, void *V_out, double *lambda,
+                   double *resid, int install, ov_eig_report *rep)
+{
+    const int k = o.k, l = o.l;
+    const long fe = (long)field_elems(c);
+    const long K = 12L * c->g.Vp;
+    const long nchunk = (K + proj_dot_chunk(K) - 1) / proj_dot_chunk(K);
+    const bool same = sizeof(S) == sizeof(double2);
+    size_t need = 4 * align_up(field_bytes<double2>(c) * k) + 2 * align_up(16ul * k * k) +
+                  align_up((size_t)nchunk * 48 * 256 * 16) + align_up(16ul * k) + 2 * align_up(8ul * (8192 + k));
+    if (!same) need += 4 * align_up(field_bytes<S>(c) * k);
+    CHK(ws_reserve(c, need));
+    EigBufs w;
+    for (auto &p : w.B) p = ws_take<double2>(c, fe * k);
+    w.G = ws_take<double2>(c, (size_t)k * k);
+    w.E = ws_take<double2>(c, (size_t)k * k);
+    w.part = ws_take<double2>(c, (size_t)nchunk * 48 * 256);
+    w.coef = ws_take<double2>(c, k);
+    w.red = ws_take<double>(c, 8192 + k);
+    w.r2 = ws_take<double>(c, 8192 + k);
+    S *FS[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (!same)
+        for (auto &p : FS) p = ws_take<S>(c, fe * k);
+    if (!w.r2 || (!same && !FS[3])) return fail(c, OV_ENOMEM, "workspace too small (internal)");
+
+    std::vector<int> grp(k, field);
+    Batch b;
+    CHK(make_batch(c, iota_vec(k), grp, b));
+    const int *fg = dev_ints(c, grp);
+    const double bnd = c->norm * c->norm;
+    double a = o.cutoff > 0 ? o.cutoff : bnd / 100.0;
+    double lref = 0.0;
+    HIPCHK(launch_pack_spinor<double2>((const double2 *)X0, w.B[0], fe, nullptr, k, c->g.V, c->g.Vp, c->stream));
+    int ix = 0;   // block holding the current X
+    std::vector<double> th(k), r(k), mu(k);
+    int it = 0;
+    long applies = 0;
+    bool conv = false;
+    while (it < o.max_iter) {
+        ++it;
+        if (a >= bnd) a = 0.5 * bnd;
+        // 1. filter
+        int iy;
+        if (same) {
+            double2 *F[3];
+            int fi = 0, ti = -1;
+            F[fi++] = w.B[ix];
+            for (int q = 0; q < 4; ++q)
+                if (q != ix) {
+                    if (fi < 3) F[fi++] = w.B[q];
+                    else ti = q;
+                }
+            int io;
+            CHK(cheb_filter<double2>(c, b, fg, F, w.B[ti], o.cheb_order, a, bnd, lref, io));
+            iy = 0;
+            for (int q = 0; q < 4; ++q)
+                if (w.B[q] == F[io]) iy = q;
+        } else {
+            S *F[3] = {FS[0], FS[1], FS[2]};
+            CHK((copy_fields<double2, S>(c, b, w.B[ix], FS[0])));
+            int io;
+            CHK(cheb_filter<S>(c, b, fg, F, FS[3], o.cheb_order, a, bnd, lref, io));
+            iy = (ix + 1) % 4;
+            CHK((copy_fields<S, double2>(c, b, F[io], w.B[iy])));
+        }
+        applies += 2L * o.cheb_order * k;
+        // 2. orthonormalise: shifted Cholesky QR, then two plain passes (ping-pong between iy and iq)
+        int iq = (iy + 1) % 4;
+        CHK(cholqr_pass(c, w.B[iy], w.B[iq], k, true, w.G, w.E, w.part));
+        CHK(cholqr_pass(c, w.B[iq], w.B[iy], k, false, w.G, w.E, w.part));
+        CHK(cholqr_pass(c, w.B[iy], w.B[iq], k, false, w.G, w.E, w.part));
+        // 3. Rayleigh-Ritz on span(Q), Q in block iq.  With H_w itself the wanted
+        //    values would be interior ones (a mix of +lambda and -lambda modes has a
+        //    Rayleigh quotient near 0), so the block is rotated by the Ritz vectors
+        //    of H_w^2 = (H_w Q)^dag (H_w Q), whose wanted values are the smallest,
+        //    and only the l lowest of those are rotated once more by the Ritz
+        //    vectors of H_w, which separates the signs.  Both rotations compose
+        //    into one k x k matrix M: X = Q M, H_w X = (H_w Q) M.
+        const int ih = (iq + 1) % 4, ixn = (iq + 2) % 4, it2 = (iq + 3) % 4;
+        CHK(dslash_launch<double2>(c, b, fg, w.B[iq], w.B[ih], 1.0, true));
+        applies += k;
+        std::vector<cd> Hq, G2, Z((size_t)k * k);
+        CHK(block_gram(c, w.B[iq], k, w.B[ih], k, w.G, w.part));
+        CHK(fetch_square(c, w.G, k, Hq));
+        CHK(block_gram(c, w.B[ih], k, w.B[ih], k, w.G, w.part));
+        CHK(fetch_square(c, w.G, k, G2));
+        ov::heev_jacobi(k, G2.data(), mu.data(), Z.data());
+        // Hs = Z_l^dag Hq Z_l
+        std::vector<cd> HZ((size_t)k * l), Hs((size_t)l * l), Y((size_t)l * l);
+        for (int j = 0; j < l; ++j)
+            for (int i = 0; i < k; ++i) {
+                cd s = 0;
+                for (int q = 0; q < k; ++q) s += Hq[i + (size_t)k * q] * Z[q + (size_t)k * j];
+                HZ[i + (size_t)k * j] = s;
+            }
+        for (int j = 0; j < l; ++j)
+            for (int i = 0; i < l; ++i) {
+                cd s = 0;
+                for (int q = 0; q < k; ++q) s += std::conj(Z[q + (size_t)k * i]) * HZ[q + (size_t)k * j];
+                Hs[i + (size_t)l * j] = s;
+            }
+        for (int j = 0; j < l; ++j)
+            for (int i = 0; i < j; ++i) {
+                const cd v = 0.5 * (Hs[i + (size_t)l * j] + std::conj(Hs[j + (size_t)l * i]));
+                Hs[i + (size_t)l * j] = v;
+                Hs[j + (size_t)l * i] = std::conj(v);
+            }
+        std::vector<double> ev(l);
+        ov::heev_jacobi(l, Hs.data(), ev.data(), Y.data());
+        std::vector<int> ord(l);
+        for (int i = 0; i < l; ++i) ord[i] = i;
+        std::stable_sort(ord.begin(), ord.end(), [&](int p, int q) { return std::fabs(ev[p]) < std::fabs(ev[q]); });
+        std::vector<cd> M(Z);
+        for (int j = 0; j < l; ++j) {
+            th[j] = ev[ord[j]];
+            for (int i = 0; i < k; ++i) {
+                cd s = 0;
+                for (int q = 0; q < l; ++q) s += Z[i + (size_t)k * q] * Y[q + (size_t)l * ord[j]];
+                M[i + (size_t)k * j] = s;
+            }
+        }
+        for (int j = l; j < k; ++j) th[j] = std::sqrt(std::max(mu[j], 0.0));
+        CHK(put_square(c, M, w.E));
+        CHK(block_rotate(c, w.B[iq], k, w.E, k, w.B[ixn]));   // X = Q M
+        CHK(block_rotate(c, w.B[ih], k, w.E, k, w.B[it2]));   // H_w X
+        // 4. residuals r_j = || H_w x_j - theta_j x_j ||
+        {
+            std::vector<double2> cf(k);
+            for (int j = 0; j < k; ++j) cf[j] = make_double2(-th[j], 0.0);
+            HIPCHK(h2d(c, w.coef, cf.data(), 16ul * k));
+            const double2 *in[2] = {w.B[it2], w.B[ixn]};
+            const double2 *cfs[2] = {nullptr, w.coef};
+            int nb = 0;
+            CHK((lincomb<double2, double2>(c, b, w.B[iq], 2, in, cfs, nullptr, 0, w.red, &nb)));
+            HIPCHK(launch_reduce_r(w.red, nb, k, w.r2, nullptr, c->stream));
+            HIPCHK(hipMemcpyAsync(r.data(), w.r2, 8ul * k, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            for (auto &v : r) v = std::sqrt(std::max(v, 0.0));
+        }
+        ix = ixn;
+        conv = true;
+        for (int j = 0; j < l; ++j) conv = conv && std::isfinite(r[j]) && r[j] <= o.tol * c->norm;
+        for (int j = 0; j < k; ++j)
+            if (!std::isfinite(th[j]) || !std::isfinite(r[j])) return fail(c, OV_ENAN, "eigensolver: non-finite Ritz pair");
+        if (conv) break;
+        // next filter: damp everything above the block's largest Ritz value of H_w^2
+        a = mu[k - 1];
+        lref = std::max(mu[0], 0.0);
+        if (!(a > lref)) a = lref + 1e-3 * bnd;
+    }
+    for (int j = 0; j < l; ++j) {
+        lambda[j] = th[j];
+        if (resid) resid[j] = r[j];
+    }
+    if (V_out)
+        HIPCHK(launch_unpack_spinor<double2>(w.B[ix], (double2 *)V_out, fe, nullptr, l, c->g.V, c->g.Vp, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (rep) {
+        rep->iters = it;
+        rep->hw_applies = applies;
+        double mr = 0;
+        for (int j = 0; j < l; ++j) mr = std::max(mr, r[j]);
+        rep->max_resid = mr;
+    }
+    if (install) CHK(install_small(c, field, l, w.B[ix], lambda));
+    if (!conv) return fail(c, OV_ENOCONV, "eigensolver: %d lowest pairs not converged to %.2e in %d passes", l, o.tol, it);
+    return OV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ov_hw_eigensolve(ov_ctx *c, int field, const ov_eig_opts *o, const void *X0_dev, void *V_dev, double *lambda,
+                     double *resid, int install, ov_eig_report *report)
+{
+    CHK(check_ctx(c));
+    if (!o || !X0_dev || !lambda) return fail(c, OV_EINVAL, "null options, start block or lambda");
+    if (field < 0 || field >= c->nfield) return fail(c, OV_EINVAL, "field %d outside [0, %d)", field, c->nfield);
+    if (!c->have_gauge) return fail(c, OV_ESTATE, "no gauge field uploaded");
+    if (!c->have_sign) return fail(c, OV_ESTATE, "sign parameters (norm bound) not set");
+    if (o->k < 1 || o->k > 256 || o->l < 1 || o->l > o->k)
+        return fail(c, OV_EINVAL, "need 1 <= l <= k <= 256 (l = %d, k = %d)", o->l, o->k);
+    if (o->cheb_order < 1 || o->cheb_order > 100000) return fail(c, OV_EINVAL, "cheb_order outside [1, 100000]");
+    if (o->max_iter < 1) return fail(c, OV_EINVAL, "max_iter must be >= 1");
+    if (!(o->tol > 0)) return fail(c, OV_EINVAL, "tol must be positive");
+    if (o->prec != OV_FP64 && o->prec != OV_FP32) return fail(c, OV_EINVAL, "filter precision must be FP64 or FP32");
+    if (o->prec == OV_FP32) return api_eigensolve<float2>(c, field, *o, X0_dev, V_dev, lambda, resid, install, report);
+    return api_eigensolve<double2>(c, field, *o, X0_dev, V_dev, lambda, resid, install, report);
 }
 
 }  // extern "C"

@@ -23,12 +23,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libov.so")
 
 OV_OK, OV_EINVAL, OV_ENOMEM, OV_EHIP, OV_ENOCONV, OV_ENAN, OV_ESTATE, OV_ENORM = 0, -1, -2, -3, -4, -5, -6, -7
+OV_EBREAKDOWN = -8
 OV_FP64, OV_FP32, OV_BF16 = 0, 1, 2
 OV_PERIODIC, OV_ANTIPERIODIC, OV_DIRICHLET = 0, 1, 2
 OV_OP_DW, OV_OP_HW = 0, 1
 PREC = {"fp64": OV_FP64, "fp32": OV_FP32, "bf16": OV_BF16}
 STATUS = {0: "OV_OK", -1: "OV_EINVAL", -2: "OV_ENOMEM", -3: "OV_EHIP", -4: "OV_ENOCONV",
-          -5: "OV_ENAN", -6: "OV_ESTATE", -7: "OV_ENORM"}
+          -5: "OV_ENAN", -6: "OV_ESTATE", -7: "OV_ENORM", -8: "OV_EBREAKDOWN"}
 
 
 class OvError(RuntimeError):
@@ -44,6 +45,15 @@ class CgOpts(C.Structure):
 
 class CgReport(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("relres", C.c_double), ("status", C.c_int)]
+
+
+class EigOpts(C.Structure):
+    _fields_ = [("l", C.c_int), ("k", C.c_int), ("cheb_order", C.c_int), ("cutoff", C.c_double),
+                ("max_iter", C.c_int), ("tol", C.c_double), ("prec", C.c_int)]
+
+
+class EigReport(C.Structure):
+    _fields_ = [("iters", C.c_int), ("hw_applies", C.c_long), ("max_resid", C.c_double)]
 
 
 def _load():
@@ -68,6 +78,8 @@ def _load():
         "ov_dov_apply": ([vp, i, i, cp(i), cp(d), i, vp, vp], i),
         "ov_deflated_cg": ([vp, i, cp(i), cp(d), vp, vp, cp(CgOpts), cp(CgReport)], i),
         "ov_sign_backward": ([vp, i, vp, vp, vp, cp(d), vp, i], i),
+        "ov_hw_eigensolve": ([vp, i, cp(EigOpts), vp, vp, cp(d), cp(d), i, cp(EigReport)], i),
+        "ov_dense_heev": ([i, cp(d), cp(d), cp(d)], i),
         "ov_prof_enable": ([vp, i], i),
         "ov_prof_query": ([vp, C.c_char_p, cp(C.c_long), cp(d), cp(d)], i),
         "ov_set_tuning": ([vp, i, i, i], i),
@@ -94,7 +106,7 @@ EXPORTED = ("ov_create", "ov_destroy", "ov_set_stream", "ov_last_error", "ov_upl
             "ov_dov_apply", "ov_deflated_cg", "ov_sign_backward", "ov_prof_enable", "ov_prof_query",
             "ov_set_tuning", "ov_get_tuning", "ov_autotune", "ov_memory_used", "ov_set_graphs",
             "ov_set_site_order", "ov_set_occupancy", "ov_get_launch_config",
-            "ov_set_launch_config")
+            "ov_set_launch_config", "ov_hw_eigensolve", "ov_dense_heev")
 
 
 def _ints(v):
@@ -117,6 +129,22 @@ def _dev(t, shape_tail, name):
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return C.c_void_p(t.data_ptr())
+
+
+def dense_heev(A):
+    """Eigen-decomposition of a Hermitian matrix by the library's host Jacobi routine
+    (ov_dense_heev): returns (ascending eigenvalues, eigenvectors as columns)."""
+    import numpy as np
+    A = np.asarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    Af = np.ascontiguousarray(A.T).view(np.float64)          # column-major, interleaved
+    w = np.zeros(n)
+    Z = np.zeros(2 * n * n)
+    rc = lib.ov_dense_heev(n, Af.ctypes.data_as(C.POINTER(C.c_double)), w.ctypes.data_as(C.POINTER(C.c_double)),
+                           Z.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != 0:
+        raise ValueError("ov_dense_heev: bad argument")
+    return w, Z.view(np.complex128).reshape(n, n).T.copy()
 
 
 class Context:
@@ -251,6 +279,32 @@ class Context:
                                        C.byref(ge) if want_eta else None,
                                        _dev(gx, (self.V, 4, 3), "gx") if want_x else None, int(ckpt_every)))
         return gU, (ge.value if want_eta else None), gx
+
+    def hw_eigensolve(self, field, l, k=None, cheb_order=60, cutoff=0.0, max_iter=20, tol=1e-10, prec="fp64",
+                      x0=None, seed=0, install=True, want_vectors=True, raise_on_noconv=True):
+        """Lowest-|lambda| eigenpairs of H_w for field group `field` (ov_hw_eigensolve).
+
+        x0: (k, V, 4, 3) complex128 start block on the device; by default seeded Gaussian
+        numbers drawn here.  Returns (lambda, resid, V or None, report)."""
+        k = int(k if k is not None else l + max(4, l // 4))
+        if x0 is None:
+            dev = f"cuda:{self.device}"
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(int(seed))
+            x0 = torch.randn((k, self.V, 4, 3), dtype=torch.complex128, device=dev, generator=gen)
+        x0 = x0.reshape(k, self.V, 4, 3).contiguous()
+        V = torch.empty((l, self.V, 4, 3), dtype=torch.complex128, device=x0.device) if want_vectors else None
+        lam = (C.c_double * l)()
+        res = (C.c_double * l)()
+        rep = EigReport()
+        opts = EigOpts(int(l), k, int(cheb_order), float(cutoff), int(max_iter), float(tol), PREC[prec])
+        rc = lib.ov_hw_eigensolve(self._h, int(field), C.byref(opts), _dev(x0, (self.V, 4, 3), "x0"),
+                                  _dev(V, (self.V, 4, 3), "V") if want_vectors else None, lam, res,
+                                  int(bool(install)), C.byref(rep))
+        if rc != OV_OK and not (rc == OV_ENOCONV and not raise_on_noconv):
+            self._chk(rc)
+        report = dict(iters=rep.iters, hw_applies=rep.hw_applies, max_resid=rep.max_resid, status=rc)
+        return list(lam), list(res), V, report
 
     # ------------------------------------------------------------ measurement and tuning
     def prof_enable(self, on=True):

@@ -1,0 +1,121 @@
+"""GPU parity of the H_w low-mode eigensolver (ov_hw_eigensolve) against the oracle.
+
+The result has a plain definition (the eigenpairs of H_w with smallest
+|lambda|), so the oracle is that definition: the dense eigendecomposition at
+4^4 and Lanczos on H_w^2 with Rayleigh-Ritz (oracle.eig) above.  Bars: FP64
+filter, tol = 1e-10 relative to the norm bound N = 6.5: eigenvalues within
+1e-10 N of the oracle (an eigenvalue error is of order residual^2 / gap),
+the oracle's own residual ||H_w v - lambda v|| of every returned vector
+within 2 tol N, and the projector onto the returned space within 1e-7 of the
+oracle's (a subspace error is of order residual / gap; l is chosen at a gap).
+An FP32 filter leaves FP32-level pollution in the subspace, so it is run to
+tol = 1e-5 and its eigenvalues checked to 1e-8 N.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import api, eig
+
+pytestmark = pytest.mark.gpu
+MW = -1.5
+NORM = 6.5
+
+
+def _ov():
+    from paper_1111_6288_amd import ov
+    return ov
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _ctx(L, bc, U, q, eta):
+    ov = _ov()
+    ctx = ov.Context(L, bc, MW)
+    ctx.upload_gauge(_t(U))
+    ctx.set_fields([q], [eta])
+    ctx.set_sign_params(20, 0.01, NORM)
+    return ctx
+
+
+def _projector_gap(Va, Vb):
+    A = Va.reshape(Va.shape[0], -1)
+    B = Vb.reshape(Vb.shape[0], -1)
+    return np.abs(A.T @ A.conj() - B.T @ B.conj()).max()
+
+
+@pytest.mark.parametrize("prec,tol,lam_bar", [("fp64", 1e-10, 1e-10), ("fp32", 1e-5, 1e-8)])
+def test_eigensolve_4x4_against_dense(prec, tol, lam_bar):
+    L, bc = (4, 4, 4, 4), (0, 0, 0, 1)
+    U = synth.su3_links(L, 0.3, 1111)
+    q, eta = 2 / 3, 0.3
+    l = 10
+    lam_d, V_d = eig.hw_low_modes_dense(L, bc, MW, U, q * eta, l + 4)
+    assert abs(abs(lam_d[l]) - abs(lam_d[l - 1])) > 1e-6
+    ctx = _ctx(L, bc, U, q, eta)
+    lam, res, V, rep = ctx.hw_eigensolve(0, l, k=24, cheb_order=40, tol=tol, prec=prec, seed=3)
+    lam = np.array(lam)
+    assert np.abs(lam - lam_d[:l]).max() < lam_bar * NORM, (lam, lam_d[:l])
+    assert max(res) <= tol * NORM
+    lat = api.Lattice(L, bc, MW, U, q * eta)
+    Vn = V.cpu().numpy()
+    assert eig.residuals(lat, lam, Vn).max() < 2 * tol * NORM
+    if prec == "fp64":
+        assert _projector_gap(Vn, V_d[:l]) < 1e-7
+    assert rep["iters"] >= 1 and rep["hw_applies"] > 0
+
+
+def test_eigensolve_ragged_dirichlet_against_lanczos():
+    """1440 sites (padded to 1472), Dirichlet in x and t, U(1) phase."""
+    L, bc = (6, 4, 6, 10), (2, 0, 0, 2)
+    U = synth.su3_links(L, 0.3, 21)
+    q, eta = -1 / 3, 0.25
+    l = 12
+    lat = api.Lattice(L, bc, MW, U, q * eta)
+    lam_o, V_o, res_o = eig.hw_low_modes(lat, l + 2)
+    assert res_o.max() < 1e-10
+    ctx = _ctx(L, bc, U, q, eta)
+    lam, res, V, rep = ctx.hw_eigensolve(0, l, k=32, cheb_order=50, tol=1e-10, seed=5)
+    lam = np.array(lam)
+    assert np.abs(lam - lam_o[:l]).max() < 1e-10 * NORM, (lam, lam_o[:l])
+    assert eig.residuals(lat, lam, V.cpu().numpy()).max() < 2e-10 * NORM
+    # orthonormal output
+    A = V.cpu().numpy().reshape(l, -1)
+    assert np.abs(A.conj() @ A.T - np.eye(l)).max() < 1e-12
+
+
+def test_installed_small_space_equals_uploaded():
+    """install=True hands the pairs to the sign function exactly as ov_upload_eigvecs would."""
+    L, bc = (4, 4, 4, 8), (0, 0, 0, 1)
+    U = synth.su3_links(L, 0.3, 8)
+    ctx = _ctx(L, bc, U, 2 / 3, 0.1)
+    ctx.set_sign_params(30, 0.02, NORM)
+    lam, res, V, rep = ctx.hw_eigensolve(0, 8, k=16, cheb_order=30, tol=1e-10, seed=1, install=True)
+    x = _t(synth.gaussian_spinors(L, 3, 2))
+    s_inst = ctx.sign_apply(x, [0, 0, 0], prec="fp64")
+    ctx.upload_eigvecs(0, V, lam)
+    s_up = ctx.sign_apply(x, [0, 0, 0], prec="fp64")
+    assert torch.equal(s_inst, s_up)
+
+
+def test_eigensolve_errors():
+    ov = _ov()
+    L, bc = (4, 4, 4, 4), (0, 0, 0, 1)
+    U = synth.su3_links(L, 0.3, 2)
+    ctx = ov.Context(L, bc, MW)
+    ctx.upload_gauge(_t(U))
+    ctx.set_fields([0.0], [0.0])
+    with pytest.raises(ov.OvError, match="OV_ESTATE"):
+        ctx.hw_eigensolve(0, 4, k=8)          # no norm bound yet
+    ctx.set_sign_params(20, 0.01, NORM)
+    with pytest.raises(ov.OvError, match="OV_EINVAL"):
+        ctx.hw_eigensolve(0, 9, k=8)
+    with pytest.raises(ov.OvError, match="OV_EINVAL"):
+        ctx.hw_eigensolve(1, 4, k=8)          # no such field group
+    with pytest.raises(ov.OvError, match="OV_ENOCONV"):
+        ctx.hw_eigensolve(0, 4, k=8, cheb_order=2, max_iter=1, tol=1e-14)
+    lam, res, V, rep = ctx.hw_eigensolve(0, 4, k=8, cheb_order=2, max_iter=1, tol=1e-14, raise_on_noconv=False)
+    assert rep["status"] == ov.OV_ENOCONV and rep["iters"] == 1 and len(lam) == 4

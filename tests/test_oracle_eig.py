@@ -6,6 +6,8 @@
   sqrt(M(p)^2 + |sin p|^2), 12-fold per momentum (H_w^2 = D_w^dag D_w is
   diagonal in momentum space).
 * Residuals ||H_w v - lambda v|| are at rounding level with the C stencil.
+* The library's host Jacobi routine used by the GPU Rayleigh-Ritz agrees with
+  numpy's eigh (the routine needs no GPU).
 """
 import numpy as np
 import pytest
@@ -64,3 +66,21 @@ def test_residual_helper_catches_a_wrong_pair():
     assert r.max() < 1e-11
     assert eig.residuals(lat, -lam, V).min() > 1e-3      # wrong sign of lambda is caught
     assert eig.residuals(lat, lam, V[::-1]).max() > 1e-6  # pairs mixed up are caught
+
+
+def test_library_host_jacobi_against_numpy():
+    ov = pytest.importorskip("paper_1111_6288_amd.ov")
+    rng = np.random.default_rng(3)
+    for n in (1, 3, 17, 64):
+        A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        A = A + A.conj().T
+        w, Z = ov.dense_heev(A)
+        assert np.abs(w - np.linalg.eigvalsh(A)).max() < 1e-12 * max(1.0, np.abs(w).max())
+        assert np.abs(A @ Z - Z * w).max() < 1e-12 * max(1.0, np.abs(w).max())
+        assert np.abs(Z.conj().T @ Z - np.eye(n)).max() < 1e-12
+    # degenerate spectrum: still an orthonormal basis
+    Q, _ = np.linalg.qr(rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8)))
+    A = (Q * np.array([1, 1, 1, 2, 2, 3, 3, 3.0])) @ Q.conj().T
+    w, Z = ov.dense_heev(A)
+    assert np.abs(w - [1, 1, 1, 2, 2, 3, 3, 3]).max() < 1e-13
+    assert np.abs(Z.conj().T @ Z - np.eye(8)).max() < 1e-13
