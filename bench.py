@@ -59,6 +59,10 @@ def parse():
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--lsmall", type=int, default=LSMALL)
     p.add_argument("--npoly", type=int, default=NPOLY)
+    p.add_argument("--eig", action="store_true",
+                   help="also time the H_w low-mode eigensolver at 24^3x48 (adds an 'eigensolver' object)")
+    p.add_argument("--eig-l", type=int, default=LSMALL)
+    p.add_argument("--eig-order", type=int, default=40)
     p.add_argument("--autotune", action="store_true",
                    help="search the dslash launch shapes instead of applying the recorded ones")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -138,6 +142,36 @@ def timed_applies(torch, ctx, x, y, fields, masses, prec, steps, warmup, prof):
             stats[cls] = ctx.prof_query(cls)
         ctx.prof_enable(False)
     return dt, stats
+
+
+def eig_measurement(torch, ov, U, args):
+    """Lowest-|lambda| eigenpairs of H_w at 24^3 x 48 for one field group (q eta = 2/3 x 1e-3):
+    Chebyshev-filtered subspace iteration, FP32 filter then FP64, to 1e-10 of the norm bound."""
+    ctx = ov.Context(L, BC, MW)
+    ctx.upload_gauge(torch.from_numpy(U).cuda())
+    ctx.set_fields([Q] * len(ETAS), list(ETAS))
+    ctx.set_sign_params(args.npoly, EPS, NORM)
+    ctx.load_tuning(TUNING_FILE, "fp32", 108)
+    ctx.load_tuning(TUNING_FILE, "fp64", 108)
+    l, k = args.eig_l, args.eig_l + max(8, args.eig_l // 8)
+    print(f"[bench] eigensolver: l={l}, k={k}, order {args.eig_order}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ctx.prof_enable(True)
+    t0 = time.perf_counter()
+    lam, res, _, rep = ctx.hw_eigensolve(1, l, k=k, cheb_order=args.eig_order, tol=1e-10, prec="fp32", seed=11,
+                                         install=False, want_vectors=False, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = {cls: ctx.prof_query(cls) for cls in ("clenshaw", "dslash", "proj_dot", "proj_expand", "blas")}
+    ctx.prof_enable(False)
+    ctx.close()
+    print(f"[bench] eigensolver: {rep['iters']} passes, {dt:.1f} s, max resid {rep['max_resid']:.2e}",
+          file=sys.stderr, flush=True)
+    return {"l": l, "k": k, "cheb_order": args.eig_order, "seconds": round(dt, 2), "passes": rep["iters"],
+            "hw_applies": rep["hw_applies"], "hw_applies_per_s": round(rep["hw_applies"] / dt, 1),
+            "converged": rep["status"] == 0, "max_resid_rel": rep["max_resid"] / NORM,
+            "lambda_min_abs": min(abs(v) for v in lam), "lambda_max_abs": max(abs(v) for v in lam),
+            "kernels_ms": {c: round(v[1], 1) for c, v in prof.items()}}
 
 
 def cpu_baseline():
@@ -262,8 +296,12 @@ def main():
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
     ctx.close()
+    if args.eig:
+        del x, y32
+        torch.cuda.empty_cache()
+        line["eigensolver"] = eig_measurement(torch, ov, U, args)
+    print(json.dumps(line), flush=True)
     if args.calibrate_copy:
         src = torch.empty(4 << 30, dtype=torch.uint8, device="cuda").fill_(1)
         dst = torch.empty_like(src)

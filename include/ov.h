@@ -199,11 +199,14 @@ int ov_deflated_cg(ov_ctx *ctx, int nrhs, const int *field_of_rhs, const double 
  * pass
  *   1. filters the block with the degree-m Chebyshev polynomial in H_w^2
  *      that damps [a, norm^2] (scaled recurrence, normalised at the lowest
- *      Ritz value of H_w^2; 2m H_w applications per vector, precision
- *      opts->prec: OV_FP64 or OV_FP32);
+ *      Ritz value of H_w^2; 2m H_w applications per vector).  opts->prec
+ *      OV_FP64: FP64 filter; OV_FP32: FP32 filter until the wanted residuals
+ *      are below 1e-6 * norm, FP64 filter after that;
  *   2. orthonormalises it in FP64 (shifted Cholesky QR, then two plain
  *      Cholesky QR passes; Gram matrices on the matrix cores);
- *   3. Rayleigh-Ritz with H_w on its span (FP64), Ritz pairs sorted by
+ *   3. Rayleigh-Ritz on its span (FP64) with H_w^2, whose wanted values are
+ *      the smallest (with H_w they would be interior ones), then with H_w
+ *      inside the l lowest to separate +lambda from -lambda; pairs sorted by
  *      |theta|; residuals r_j = ||H_w x_j - theta_j x_j|| (unit x_j).
  * It stops when the l lowest satisfy r_j <= tol * norm, or after max_iter
  * passes.  The first pass uses a = opts->cutoff (in units of H_w^2; <= 0:
@@ -225,7 +228,7 @@ typedef struct {
     double cutoff;     /* first-pass lower end a of the damped interval, in units of H_w^2     */
     int max_iter;      /* passes                                                               */
     double tol;        /* residual bound relative to the norm bound                            */
-    int prec;          /* filter precision: OV_FP64 or OV_FP32                                 */
+    int prec;          /* OV_FP64, or OV_FP32: FP32 filter down to 1e-6 * norm, then FP64       */
 } ov_eig_opts;
 
 typedef struct {

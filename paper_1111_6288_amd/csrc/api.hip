@@ -2008,18 +2008,22 @@ int install_small(ov_ctx *c, int field, int l, const double2 *Vplanes, const dou
     return OV_OK;
 }
 
-template <class S>
+// FP32 filter (o.prec == OV_FP32) while the wanted residuals exceed
+// kFp32Floor * norm, FP64 filter afterwards.
+constexpr double kFp32Floor = 1e-6;
+
 int api_eigensolve(ov_ctx *c, int field, const ov_eig_opts &o, const void *X0, void *V_out, double *lambda,
                    double *resid, int install, ov_eig_report *rep)
 {
+    using S = float2;
     const int k = o.k, l = o.l;
     const long fe = (long)field_elems(c);
     const long K = 12L * c->g.Vp;
     const long nchunk = (K + proj_dot_chunk(K) - 1) / proj_dot_chunk(K);
-    const bool same = sizeof(S) == sizeof(double2);
+    const bool has32 = o.prec == OV_FP32;
     size_t need = 4 * align_up(field_bytes<double2>(c) * k) + 2 * align_up(16ul * k * k) +
                   align_up((size_t)nchunk * 48 * 256 * 16) + align_up(16ul * k) + 2 * align_up(8ul * (8192 + k));
-    if (!same) need += 4 * align_up(field_bytes<S>(c) * k);
+    if (has32) need += 4 * align_up(field_bytes<S>(c) * k);
     CHK(ws_reserve(c, need));
     EigBufs w;
     for (auto &p : w.B) p = ws_take<double2>(c, fe * k);
@@ -2030,9 +2034,10 @@ int api_eigensolve(ov_ctx *c, int field, const ov_eig_opts &o, const void *X0, v
     w.red = ws_take<double>(c, 8192 + k);
     w.r2 = ws_take<double>(c, 8192 + k);
     S *FS[4] = {nullptr, nullptr, nullptr, nullptr};
-    if (!same)
+    if (has32)
         for (auto &p : FS) p = ws_take<S>(c, fe * k);
-    if (!w.r2 || (!same && !FS[3])) return fail(c, OV_ENOMEM, "workspace too small (internal)");
+    if (!w.r2 || (has32 && !FS[3])) return fail(c, OV_ENOMEM, "workspace too small (internal)");
+    bool use32 = has32;   // switched off once the FP32 floor is reached
 
     std::vector<int> grp(k, field);
     Batch b;
@@ -2052,7 +2057,7 @@ int api_eigensolve(ov_ctx *c, int field, const ov_eig_opts &o, const void *X0, v
         if (a >= bnd) a = 0.5 * bnd;
         // 1. filter
         int iy;
-        if (same) {
+        if (!use32) {
             double2 *F[3];
             int fi = 0, ti = -1;
             F[fi++] = w.B[ix];
@@ -2150,7 +2155,12 @@ int api_eigensolve(ov_ctx *c, int field, const ov_eig_opts &o, const void *X0, v
         }
         ix = ixn;
         conv = true;
-        for (int j = 0; j < l; ++j) conv = conv && std::isfinite(r[j]) && r[j] <= o.tol * c->norm;
+        double rmax = 0;
+        for (int j = 0; j < l; ++j) {
+            conv = conv && std::isfinite(r[j]) && r[j] <= o.tol * c->norm;
+            rmax = std::max(rmax, r[j]);
+        }
+        if (use32 && rmax <= kFp32Floor * c->norm) use32 = false;
         for (int j = 0; j < k; ++j)
             if (!std::isfinite(th[j]) || !std::isfinite(r[j])) return fail(c, OV_ENAN, "eigensolver: non-finite Ritz pair");
         if (conv) break;
@@ -2196,8 +2206,7 @@ int ov_hw_eigensolve(ov_ctx *c, int field, const ov_eig_opts *o, const void *X0_
     if (o->max_iter < 1) return fail(c, OV_EINVAL, "max_iter must be >= 1");
     if (!(o->tol > 0)) return fail(c, OV_EINVAL, "tol must be positive");
     if (o->prec != OV_FP64 && o->prec != OV_FP32) return fail(c, OV_EINVAL, "filter precision must be FP64 or FP32");
-    if (o->prec == OV_FP32) return api_eigensolve<float2>(c, field, *o, X0_dev, V_dev, lambda, resid, install, report);
-    return api_eigensolve<double2>(c, field, *o, X0_dev, V_dev, lambda, resid, install, report);
+    return api_eigensolve(c, field, *o, X0_dev, V_dev, lambda, resid, install, report);
 }
 
 }  // extern "C"

@@ -24,16 +24,18 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // j + 16k, and D[i][j] lands in lane j + 16 (i mod 4), register i div 4; so
 // lane q, register r holds row 4r + q/16, column q%16.
 //
-// Workgroup = 4 waves; it owns one K-chunk.  Wave w owns vector tiles
-// w, w+4, ... (up to MT tiles) and all RHS tiles (up to NT).  Per MFMA step
+// Workgroup = W waves (W = blockDim / 64, at most 8); it owns one K-chunk.
+// Wave w owns vector tiles w, w+W, ... (up to MT tiles) and all RHS tiles (up
+// to NT); the launcher picks W = ceil(tiles / MT).  Per MFMA step
 // lane q holds A[i = q%16][k = q/16] = V and B[k = q/16][j = q%16] = X.
 template <class S, int MT, int NT>
-__global__ __launch_bounds__(256) void k_proj_dot_mfma(const double2 *__restrict__ V, int l, long vstride,
+__global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict__ V, int l, long vstride,
                                                        const S *__restrict__ X, long xstride,
                                                        const int *slots, int n, int Vp, int g5x, long chunk,
                                                        double2 *__restrict__ part)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int W = blockDim.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const long K = 12L * Vp, half = 6L * Vp;
     const long k0 = (long)blockIdx.x * chunk;
@@ -53,7 +55,7 @@ __global__ __launch_bounds__(256) void k_proj_dot_mfma(const double2 *__restrict
     bool vok[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-        const int i = (wave + 4 * m) * 16 + row;
+        const int i = (wave + W * m) * 16 + row;
         vok[m] = i < l;
         vp[m] = V + (long)(vok[m] ? i : 0) * vstride;
     }
@@ -70,7 +72,11 @@ __global__ __launch_bounds__(256) void k_proj_dot_mfma(const double2 *__restrict
     // (plane, site) of kb, advanced with it: kb and Vp are multiples of 4, so
     // kb + kq stays in the plane of kb
     long pl = k0 / Vp, st = k0 - pl * Vp;
-    for (long kb = k0; kb < k1; kb += 4) {
+    // The loads of step kb + 4 are issued before the matrix-core work of step
+    // kb (one wave per SIMD fits, so nothing else would hide their latency).
+    double2 vn[MT];
+    cx<double> xn[NT];
+    auto load_step = [&](long kb) {
         const long k = kb + kq;
         const bool kin = k < k1;
         const long xk = cpos<S>((int)pl, st + kq, Vp);
@@ -79,17 +85,30 @@ __global__ __launch_bounds__(256) void k_proj_dot_mfma(const double2 *__restrict
             st -= Vp;
             ++pl;
         }
-        double xr[NT], xi[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             cx<double> x = (kin && xok[t]) ? ldc<double>(xp[t], xk) : cx<double>{0.0, 0.0};
             if (g5x && k >= half) x = {-x.x, -x.y};
-            xr[t] = x.x;
-            xi[t] = x.y;
+            xn[t] = x;
         }
 #pragma unroll
+        for (int m = 0; m < MT; ++m) vn[m] = (kin && vok[m]) ? vp[m][k] : make_double2(0.0, 0.0);
+    };
+    if (k0 < k1) load_step(k0);
+    for (long kb = k0; kb < k1; kb += 4) {
+        double2 vc[MT];
+        double xr[NT], xi[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            xr[t] = xn[t].x;
+            xi[t] = xn[t].y;
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m) vc[m] = vn[m];
+        if (kb + 4 < k1) load_step(kb + 4);
+#pragma unroll
         for (int m = 0; m < MT; ++m) {
-            double2 v = (kin && vok[m]) ? vp[m][k] : make_double2(0.0, 0.0);
+            const double2 v = vc[m];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 // Re: vr xr + vi xi ; Im: vr xi - vi xr
@@ -109,7 +128,7 @@ __global__ __launch_bounds__(256) void k_proj_dot_mfma(const double2 *__restrict
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = (wave + 4 * m) * 16 + 4 * r + kq;
+                const int i = (wave + W * m) * 16 + 4 * r + kq;
                 const int j = t * 16 + row;
                 if (i < l && j < n) pc[(long)j * l + i] = make_double2(cre[m][t][r], cim[m][t][r]);
             }
@@ -221,10 +240,10 @@ long proj_dot_chunk(long K)
 
 template <class S, int MT, int NT>
 static void launch_dot_mt(const double2 *V, int l, long vstride, const S *X, long xstride, const int *slots,
-                          int n, int Vp, int g5x, long chunk, int nchunk, double2 *part, hipStream_t st)
+                          int n, int Vp, int g5x, long chunk, int nchunk, double2 *part, int waves, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_proj_dot_mfma<S, MT, NT>), dim3(nchunk), dim3(256), 0, st, V, l, vstride, X, xstride,
-                       slots, n, Vp, g5x, chunk, part);
+    hipLaunchKernelGGL((k_proj_dot_mfma<S, MT, NT>), dim3(nchunk), dim3(64 * waves), 0, st, V, l, vstride, X,
+                       xstride, slots, n, Vp, g5x, chunk, part);
 }
 
 template <class S>
@@ -236,14 +255,17 @@ hipError_t launch_proj_dot(const double2 *V, int l, long vstride, const S *X, lo
     const long K = 12L * Vp;
     const long chunk = proj_dot_chunk(K);
     const int nchunk = (int)((K + chunk - 1) / chunk);
-    const int mt = ((l + 15) / 16 + 3) / 4;   // vector tiles per wave
+    // two vector tiles per wave, as many waves as that takes (<= 8): few idle
+    // tile slots, and the accumulators leave room for two waves per SIMD
+    const int tiles = (l + 15) / 16;
+    const int mt = tiles >= 2 ? 2 : 1;
+    const int waves = (tiles + mt - 1) / mt;
     const int nt = (n + 15) / 16;
 #define OV_DOT_CASE(M, N) \
-    if (mt == M && nt == N) launch_dot_mt<S, M, N>(V, l, vstride, X, xstride, slots, n, Vp, g5x, chunk, nchunk, part, st)
+    if (mt == M && nt == N) \
+    launch_dot_mt<S, M, N>(V, l, vstride, X, xstride, slots, n, Vp, g5x, chunk, nchunk, part, waves, st)
     OV_DOT_CASE(1, 1); else OV_DOT_CASE(1, 2); else OV_DOT_CASE(1, 3);
     else OV_DOT_CASE(2, 1); else OV_DOT_CASE(2, 2); else OV_DOT_CASE(2, 3);
-    else OV_DOT_CASE(3, 1); else OV_DOT_CASE(3, 2); else OV_DOT_CASE(3, 3);
-    else OV_DOT_CASE(4, 1); else OV_DOT_CASE(4, 2); else OV_DOT_CASE(4, 3);
     else return hipErrorInvalidValue;
 #undef OV_DOT_CASE
     const int nl = n * l;

@@ -8,8 +8,9 @@ filter, tol = 1e-10 relative to the norm bound N = 6.5: eigenvalues within
 the oracle's own residual ||H_w v - lambda v|| of every returned vector
 within 2 tol N, and the projector onto the returned space within 1e-7 of the
 oracle's (a subspace error is of order residual / gap; l is chosen at a gap).
-An FP32 filter leaves FP32-level pollution in the subspace, so it is run to
-tol = 1e-5 and its eigenvalues checked to 1e-8 N.
+An FP32 filter leaves FP32-level pollution in the subspace: run to
+tol = 1e-5 alone, its eigenvalues are checked to 1e-8 N; asked for 1e-10 it
+hands over to FP64 passes and meets the FP64 bars.
 """
 import numpy as np
 import pytest
@@ -47,7 +48,7 @@ def _projector_gap(Va, Vb):
     return np.abs(A.T @ A.conj() - B.T @ B.conj()).max()
 
 
-@pytest.mark.parametrize("prec,tol,lam_bar", [("fp64", 1e-10, 1e-10), ("fp32", 1e-5, 1e-8)])
+@pytest.mark.parametrize("prec,tol,lam_bar", [("fp64", 1e-10, 1e-10), ("fp32", 1e-5, 1e-8), ("fp32", 1e-10, 1e-10)])
 def test_eigensolve_4x4_against_dense(prec, tol, lam_bar):
     L, bc = (4, 4, 4, 4), (0, 0, 0, 1)
     U = synth.su3_links(L, 0.3, 1111)
@@ -63,7 +64,7 @@ def test_eigensolve_4x4_against_dense(prec, tol, lam_bar):
     lat = api.Lattice(L, bc, MW, U, q * eta)
     Vn = V.cpu().numpy()
     assert eig.residuals(lat, lam, Vn).max() < 2 * tol * NORM
-    if prec == "fp64":
+    if tol <= 1e-10:
         assert _projector_gap(Vn, V_d[:l]) < 1e-7
     assert rep["iters"] >= 1 and rep["hw_applies"] > 0
 
