@@ -62,7 +62,9 @@ def parse():
     p.add_argument("--eig", action="store_true",
                    help="also time the H_w low-mode eigensolver at 24^3x48 (adds an 'eigensolver' object)")
     p.add_argument("--eig-l", type=int, default=LSMALL)
-    p.add_argument("--eig-order", type=int, default=40)
+    p.add_argument("--eig-order", type=int, default=100)
+    p.add_argument("--eig-k", type=int, default=256)
+    p.add_argument("--eig-maxiter", type=int, default=12)
     p.add_argument("--autotune", action="store_true",
                    help="search the dslash launch shapes instead of applying the recorded ones")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -153,13 +155,14 @@ def eig_measurement(torch, ov, U, args):
     ctx.set_sign_params(args.npoly, EPS, NORM)
     ctx.load_tuning(TUNING_FILE, "fp32", 108)
     ctx.load_tuning(TUNING_FILE, "fp64", 108)
-    l, k = args.eig_l, args.eig_l + max(8, args.eig_l // 8)
+    l, k = args.eig_l, max(args.eig_k, args.eig_l)
     print(f"[bench] eigensolver: l={l}, k={k}, order {args.eig_order}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ctx.prof_enable(True)
     t0 = time.perf_counter()
     lam, res, _, rep = ctx.hw_eigensolve(1, l, k=k, cheb_order=args.eig_order, tol=1e-10, prec="fp32", seed=11,
-                                         install=False, want_vectors=False, raise_on_noconv=False)
+                                         max_iter=args.eig_maxiter, install=False, want_vectors=False,
+                                         raise_on_noconv=False)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = {cls: ctx.prof_query(cls) for cls in ("clenshaw", "dslash", "proj_dot", "proj_expand", "blas")}
