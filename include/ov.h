@@ -192,6 +192,49 @@ int ov_deflated_cg(ov_ctx *ctx, int nrhs, const int *field_of_rhs, const double 
                    ov_cg_rhs_report *report);
 
 /*
+ * Quark propagators for several masses at once (Sec. 3.2: adaptive
+ * multi-mass CG, with the polynomial order following the CG residual).  For
+ * a source of definite chirality (gamma5 b = chi b; point sources are), and
+ * with s^2 = 1, D(m)^dag D(m) restricted to that chirality is
+ *   (1 - m^2/4) (A + sigma),  A = 2 + 2 P s P,  sigma = m^2 / (1 - m^2/4),
+ * P = (1 + chi gamma5)/2, so one sign application per iteration serves every
+ * mass: shifted CG on A (base system = smallest shift), y_i = (A +
+ * sigma_i)^{-1} b / (1 - m_i^2/4), x_i = D(m_i)^dag y_i, which solves
+ * D(m_i) x_i = b because D is normal.  With opts->adaptive the degree of the
+ * polynomial for an iteration is the smallest whose error bound (twice the
+ * law of eq. (2)) stays below 0.1 tol ||b|| / ||r|| (a less accurate operator
+ * is enough while the residual is large), at least min_order; the context's
+ * polynomial is restored afterwards.  The shifted solve runs in
+ * opts->inner_prec (FP64, or FP32 down to max(tol, 1e-6)); then every x_i
+ * gets its FP64 true residual ||b - D(m_i) x_i|| / ||b|| with the full
+ * polynomial, and with opts->refine pairs above tol are finished by the
+ * FP64-outer deflated CG of ov_deflated_cg, starting from x_i.
+ *   b_dev  [nrhs][V][4][3] complex128 chiral sources;
+ *   x_dev  [nmass][nrhs][V][4][3] complex128 solutions (written);
+ *   relres host [nmass][nrhs] final relative residuals (may be NULL).
+ * OV_EINVAL for a source with both chiralities.  Synchronises.
+ */
+typedef struct {
+    double tol;        /* FP64 true relative residual per (mass, RHS)                           */
+    int maxiter;       /* shifted CG iterations (one sign application per RHS each)             */
+    int adaptive;      /* polynomial order follows the residual                                 */
+    int min_order;     /* lower bound of the adaptive order                                      */
+    int refine;        /* finish pairs above tol with the deflated CG                            */
+    int inner_prec;    /* precision of the shifted solve: OV_FP64 or OV_FP32                     */
+} ov_mscg_opts;
+
+typedef struct {
+    int iters;          /* shifted CG iterations                                                 */
+    long sign_applies;  /* single-vector sign applications in the shifted solve                  */
+    long dslash_applies;/* single-vector H_w applications in the shifted solve                    */
+    int refine_iters;   /* inner CG iterations spent in refinement (summed over RHS)              */
+} ov_mscg_report;
+
+int ov_multishift_cg(ov_ctx *ctx, int nrhs, const int *field_of_rhs, int nmass, const double *mass,
+                     const void *b_dev, void *x_dev, const ov_mscg_opts *opts, ov_mscg_report *report,
+                     double *relres);
+
+/*
  * Lowest-|lambda| eigenpairs of H_w for field group `field`: the low modes
  * that the sign function treats exactly (Sec. 2, Fig. 1), which the paper
  * computes by Arnoldi with Chebyshev acceleration (Sec. 3.1).  Here:

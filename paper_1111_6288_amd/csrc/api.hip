@@ -2210,3 +2210,315 @@ int ov_hw_eigensolve(ov_ctx *c, int field, const ov_eig_opts *o, const void *X0_
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- multi-mass CG in a chirality sector
+namespace {
+
+// Order of the adaptive polynomial: the smallest n whose error bound
+// 2 * 0.41 exp(-2.1 n sqrt(eps)) (twice the law of eq. (2), which the
+// interpolant stays below) is within `err`, clamped to [nmin, nmax].
+int adaptive_order(double err, double eps, int nmin, int nmax)
+{
+    if (!(err > 0)) return nmax;
+    const double n = std::log(0.82 / err) / (2.1 * std::sqrt(eps));
+    const int ni = (int)std::ceil(n);
+    return std::max(nmin, std::min(nmax, ni));
+}
+
+template <class S>
+int api_mscg(ov_ctx *c, int nrhs, const std::vector<int> &grp, int nm, const double *mass, const void *b_dev,
+             void *x_dev, const ov_mscg_opts &o, ov_mscg_report *rep, double *relres)
+{
+    const long fe = (long)field_elems(c);
+    const int n = nrhs;
+    // shifts sigma_i = m_i^2 / (1 - m_i^2 / 4); the base system is the smallest shift
+    std::vector<double> sig(nm), fac(nm);
+    int base = 0;
+    for (int i = 0; i < nm; ++i) {
+        fac[i] = 1.0 - 0.25 * mass[i] * mass[i];
+        sig[i] = mass[i] * mass[i] / fac[i];
+        if (sig[i] < sig[base]) base = i;
+    }
+    // workspace: FP64 sources and output staging; S-precision r, Ap, u, p[nm], y[nm]; sign buffers
+    const size_t f64 = align_up(field_bytes<double2>(c) * n);
+    const size_t fS = align_up(field_bytes<S>(c) * n);
+    const size_t need = 2 * f64 + (3 + 2 * (size_t)nm) * fS +
+                        std::max(sign_bufs_bytes<S>(c, n), dov_bufs_bytes<double2>(c, n) + f64) +
+                        3 * align_up(16ul * n) + align_up(16ul * (8192 + n)) + 2 * align_up(8ul * (8192 + n));
+    CHK(ws_reserve(c, need));
+    double2 *B64 = ws_take<double2>(c, fe * n), *X64 = ws_take<double2>(c, fe * n);
+    S *r = ws_take<S>(c, fe * n), *Ap = ws_take<S>(c, fe * n), *u = ws_take<S>(c, fe * n);
+    std::vector<S *> p(nm), y(nm);
+    for (int i = 0; i < nm; ++i) p[i] = ws_take<S>(c, fe * n);
+    for (int i = 0; i < nm; ++i) y[i] = ws_take<S>(c, fe * n);
+    double2 *cf0 = ws_take<double2>(c, n), *cf1 = ws_take<double2>(c, n), *dots = ws_take<double2>(c, n);
+    double2 *dpart = ws_take<double2>(c, 8192 + n);
+    double *red = ws_take<double>(c, 8192 + n), *rr_d = ws_take<double>(c, 8192 + n);
+    const size_t mark = c->ws_top;
+    SignBufs<S> sb;
+    CHK(take_sign_bufs<S>(c, n, sb));
+    if (!rr_d) return fail(c, OV_ENOMEM, "workspace too small (internal)");
+
+    Batch ball;
+    CHK(make_batch(c, iota_vec(n), grp, ball));
+    const int *fg = dev_ints(c, grp);
+    HIPCHK(launch_pack_spinor<double2>((const double2 *)b_dev, B64, fe, nullptr, n, c->g.V, c->g.Vp, c->stream));
+
+    // chirality of each source: ||P- b||^2 = (||b||^2 - <b, g5 b>) / 2
+    std::vector<double> bn2(n), chi(n);
+    {
+        std::vector<double2> h(n);
+        HIPCHK((launch_dot<double2, double2>(B64, fe, B64, fe, nullptr, n, c->g.Vp, 0, dpart, dots, nullptr, c->stream)));
+        HIPCHK(hipMemcpyAsync(h.data(), dots, 16ul * n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int j = 0; j < n; ++j) bn2[j] = h[j].x;
+        HIPCHK((launch_dot<double2, double2>(B64, fe, B64, fe, nullptr, n, c->g.Vp, 1, dpart, dots, nullptr, c->stream)));
+        HIPCHK(hipMemcpyAsync(h.data(), dots, 16ul * n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int j = 0; j < n; ++j) {
+            if (!std::isfinite(bn2[j]) || !(bn2[j] > 0)) return fail(c, OV_EINVAL, "source %d is zero or non-finite", j);
+            const double minus = 0.5 * (bn2[j] - h[j].x), plus = 0.5 * (bn2[j] + h[j].x);
+            if (minus <= 1e-24 * bn2[j]) chi[j] = 1.0;
+            else if (plus <= 1e-24 * bn2[j]) chi[j] = -1.0;
+            else return fail(c, OV_EINVAL, "source %d has both chiralities (needs gamma5 b = +-b)", j);
+        }
+    }
+    // r = b, p_i = b, y_i = 0
+    CHK((copy_fields<double2, S>(c, ball, B64, r)));
+    for (int i = 0; i < nm; ++i) {
+        CHK((copy_fields<double2, S>(c, ball, B64, p[i])));
+        const S *in[1] = {r};
+        const double2 zero = make_double2(0, 0);
+        CHK((lincomb<S, S>(c, ball, y[i], 1, in, nullptr, &zero, 0)));
+    }
+    std::vector<double> rr(bn2);   // (r, r) per RHS
+    std::vector<double> zeta(nm * n, 1.0), zeta_old(nm * n, 1.0), alpha_old(n, 1.0), beta_old(n, 0.0);
+    std::vector<char> done(nm * n, 0);
+    // the adaptive order swaps the context's polynomial; the guard puts it back on every exit
+    struct PolyGuard {
+        ov_ctx *c;
+        int n;
+        std::vector<double> coef;
+        ~PolyGuard()
+        {
+            c->npoly = n;
+            c->coef = coef;
+        }
+    } guard{c, c->npoly, c->coef};
+    const int n_full = guard.n;
+    const std::vector<double> &coef_full = guard.coef;
+    int cur_order = n_full;
+    const double inner_tol = (sizeof(S) == sizeof(double2)) ? o.tol : std::max(o.tol, 1e-6);
+    int it = 0;
+    long sign_applies = 0, dslash_applies = 0;
+    int rc = OV_OK;
+    for (; it < o.maxiter; ++it) {
+        double rho = 0;
+        bool all = true;
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < nm; ++i) {
+                const double res = std::fabs(zeta[i * n + j]) * std::sqrt(rr[j] / bn2[j]);
+                if (res <= inner_tol) done[i * n + j] = 1;
+                all = all && done[i * n + j];
+                if (!done[i * n + j]) rho = std::max(rho, res);
+            }
+        if (all) break;
+        // 1. order of this application (relaxation: the operator may be less accurate
+        //    as the residual falls)
+        if (o.adaptive) {
+            const int ord = adaptive_order(0.1 * inner_tol / std::max(rho, 1e-300), c->eps, o.min_order, n_full);
+            if (ord != cur_order) {
+                cur_order = ord;
+                c->npoly = ord;
+                if (ord == n_full) c->coef = coef_full;
+                else cheb_interp(ord, c->eps, c->coef);
+            }
+        }
+        // 2. Ap = (A + sigma_b) p_b,  A v = 2 v + chi s v + g5 s v  (v in the sector of chi)
+        rc = sign_batch<S>(c, ball, fg, p[base], u, sb);
+        if (rc != OV_OK) break;
+        sign_applies += n;
+        dslash_applies += (long)n * (2 * cur_order + 1);
+        {
+            std::vector<double2> h0(n), h1(n);
+            for (int j = 0; j < n; ++j) {
+                h0[j] = make_double2(2.0 + sig[base], 0.0);
+                h1[j] = make_double2(chi[j], 0.0);
+            }
+            HIPCHK(h2d(c, cf0, h0.data(), 16ul * n));
+            HIPCHK(h2d(c, cf1, h1.data(), 16ul * n));
+            const S *in[3] = {p[base], u, u};
+            const double2 *cfs[3] = {cf0, cf1, nullptr};
+            const double2 cc[3] = {make_double2(1, 0), make_double2(1, 0), make_double2(1, 0)};
+            CHK((lincomb<S, S>(c, ball, Ap, 3, in, cfs, cc, 4)));
+        }
+        // 3. alpha = (r, r) / (p_b, Ap)
+        std::vector<double2> h(n);
+        HIPCHK((launch_dot<S, S>(p[base], fe, Ap, fe, nullptr, n, c->g.Vp, 0, dpart, dots, nullptr, c->stream)));
+        HIPCHK(hipMemcpyAsync(h.data(), dots, 16ul * n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        std::vector<double> alpha(n), zeta_new(nm * n), alpha_s(nm * n);
+        for (int j = 0; j < n; ++j) {
+            alpha[j] = h[j].x > 0 ? rr[j] / h[j].x : 0.0;
+            for (int i = 0; i < nm; ++i) {
+                const int q = i * n + j;
+                const double ds = sig[i] - sig[base];
+                const double den = alpha[j] * beta_old[j] * (zeta_old[q] - zeta[q]) +
+                                   zeta_old[q] * alpha_old[j] * (1.0 + ds * alpha[j]);
+                zeta_new[q] = (den != 0) ? zeta[q] * zeta_old[q] * alpha_old[j] / den : 0.0;
+                alpha_s[q] = (zeta[q] != 0) ? alpha[j] * zeta_new[q] / zeta[q] : 0.0;
+                if (done[q]) alpha_s[q] = 0.0;   // converged systems are frozen
+            }
+        }
+        // 4. y_i += alpha_i p_i
+        for (int i = 0; i < nm; ++i) {
+            std::vector<double2> hc(n);
+            bool any = false;
+            for (int j = 0; j < n; ++j) {
+                hc[j] = make_double2(alpha_s[i * n + j], 0.0);
+                any = any || !done[i * n + j];
+            }
+            if (!any) continue;
+            HIPCHK(h2d(c, cf0, hc.data(), 16ul * n));
+            const S *in[2] = {y[i], p[i]};
+            const double2 *cfs[2] = {nullptr, cf0};
+            CHK((lincomb<S, S>(c, ball, y[i], 2, in, cfs, nullptr, 0)));
+        }
+        // 5. r -= alpha Ap, with (r, r)
+        {
+            std::vector<double2> hc(n);
+            for (int j = 0; j < n; ++j) hc[j] = make_double2(-alpha[j], 0.0);
+            HIPCHK(h2d(c, cf0, hc.data(), 16ul * n));
+            const S *in[2] = {r, Ap};
+            const double2 *cfs[2] = {nullptr, cf0};
+            int nb = 0;
+            CHK((lincomb<S, S>(c, ball, r, 2, in, cfs, nullptr, 0, red, &nb)));
+            HIPCHK(launch_reduce_r(red, nb, n, rr_d, nullptr, c->stream));
+        }
+        std::vector<double> rr_new(n);
+        HIPCHK(hipMemcpyAsync(rr_new.data(), rr_d, 8ul * n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        // 6. p_i = zeta_new_i r + beta_i p_i
+        std::vector<double> beta(n);
+        for (int j = 0; j < n; ++j) beta[j] = rr[j] > 0 ? rr_new[j] / rr[j] : 0.0;
+        for (int i = 0; i < nm; ++i) {
+            std::vector<double2> ha(n), hb(n);
+            bool any = false;
+            for (int j = 0; j < n; ++j) {
+                const int q = i * n + j;
+                const double bs = (zeta[q] != 0) ? beta[j] * (zeta_new[q] / zeta[q]) * (zeta_new[q] / zeta[q]) : 0.0;
+                ha[j] = make_double2(zeta_new[q], 0.0);
+                hb[j] = make_double2(bs, 0.0);
+                any = any || !done[q] || i == base;
+            }
+            if (!any) continue;
+            HIPCHK(h2d(c, cf0, ha.data(), 16ul * n));
+            HIPCHK(h2d(c, cf1, hb.data(), 16ul * n));
+            const S *in[2] = {r, p[i]};
+            const double2 *cfs[2] = {cf0, cf1};
+            CHK((lincomb<S, S>(c, ball, p[i], 2, in, cfs, nullptr, 0)));
+        }
+        for (int j = 0; j < n; ++j) {
+            if (!std::isfinite(rr_new[j])) return fail(c, OV_ENAN, "multi-mass CG: non-finite residual for RHS %d", j);
+            alpha_old[j] = alpha[j];
+            beta_old[j] = beta[j];
+            rr[j] = rr_new[j];
+        }
+        for (int q = 0; q < nm * n; ++q) {
+            zeta_old[q] = zeta[q];
+            zeta[q] = zeta_new[q];
+        }
+    }
+    CHK(rc);
+    c->npoly = n_full;
+    c->coef = coef_full;
+    // x_i = D(m_i)^dag y_i / (1 - m_i^2 / 4), then the FP64 true residual of D(m_i) x_i = b
+    c->ws_top = mark;
+    double2 *T64 = ws_take<double2>(c, fe * n);
+    DovBufs<double2> dw;
+    CHK(take_dov_bufs<double2>(c, n, dw));
+    std::vector<double> rel(nm * n, 0.0);
+    for (int i = 0; i < nm; ++i) {
+        const double2 sc = make_double2(1.0 / fac[i], 0.0);
+        const S *in[1] = {y[i]};
+        CHK((lincomb<S, double2>(c, ball, X64, 1, in, nullptr, &sc, 0)));
+        std::vector<double> mv(n, mass[i]);
+        const double2 *ca, *cb;
+        CHK(mass_coefs(c, n, mv.data(), &ca, &cb));
+        CHK(dov_batch<double2>(c, ball, fg, ca, cb, true, X64, T64, dw));
+        HIPCHK(launch_unpack_spinor<double2>(T64, (double2 *)x_dev + (size_t)i * n * 12 * c->g.V, fe, nullptr, n,
+                                             c->g.V, c->g.Vp, c->stream));
+        CHK(dov_batch<double2>(c, ball, fg, ca, cb, false, T64, X64, dw));
+        const double2 *in2[2] = {B64, X64};
+        const double2 cc2[2] = {make_double2(1, 0), make_double2(-1, 0)};
+        int nb = 0;
+        CHK((lincomb<double2, double2>(c, ball, X64, 2, in2, nullptr, cc2, 0, red, &nb)));
+        HIPCHK(launch_reduce_r(red, nb, n, rr_d, nullptr, c->stream));
+        std::vector<double> h(n);
+        HIPCHK(hipMemcpyAsync(h.data(), rr_d, 8ul * n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int j = 0; j < n; ++j) rel[i * n + j] = std::sqrt(std::max(h[j], 0.0) / bn2[j]);
+    }
+    int refine_iters = 0;
+    if (o.refine) {
+        for (int i = 0; i < nm; ++i) {
+            bool need_ref = false;
+            for (int j = 0; j < n; ++j) need_ref = need_ref || rel[i * n + j] > o.tol;
+            if (!need_ref) continue;
+            ov_cg_opts co{};
+            co.tol = o.tol;
+            co.maxiter = o.maxiter;
+            co.inner_prec = OV_FP32;
+            co.inner_tol = 1e-5;
+            co.max_restarts = 50;
+            co.use_deflation = 1;
+            std::vector<double> mv(n, mass[i]);
+            std::vector<ov_cg_rhs_report> cr(n);
+            const int r2 = api_cg<float2>(c, n, grp, mv.data(), b_dev, (double2 *)x_dev + (size_t)i * n * 12 * c->g.V,
+                                          co, cr.data());
+            for (int j = 0; j < n; ++j) {
+                rel[i * n + j] = cr[j].relres;
+                refine_iters += cr[j].iters;
+            }
+            if (r2 != OV_OK && r2 != OV_ENOCONV) return r2;
+        }
+    }
+    if (relres)
+        for (int q = 0; q < nm * n; ++q) relres[q] = rel[q];
+    if (rep) {
+        rep->iters = it;
+        rep->sign_applies = sign_applies;
+        rep->dslash_applies = dslash_applies;
+        rep->refine_iters = refine_iters;
+    }
+    for (int q = 0; q < nm * n; ++q)
+        if (!(rel[q] <= o.tol)) return fail(c, OV_ENOCONV, "multi-mass CG: pair %d at %.3e > tol %.3e", q, rel[q], o.tol);
+    return OV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ov_multishift_cg(ov_ctx *c, int nrhs, const int *field_of_rhs, int nmass, const double *mass, const void *b_dev,
+                     void *x_dev, const ov_mscg_opts *o, ov_mscg_report *report, double *relres)
+{
+    CHK(check_ctx(c));
+    if (!o || !mass || !b_dev || !x_dev) return fail(c, OV_EINVAL, "null argument");
+    if (!c->have_gauge) return fail(c, OV_ESTATE, "no gauge field uploaded");
+    if (!c->have_sign) return fail(c, OV_ESTATE, "sign parameters not set");
+    if (nmass < 1 || nmass > 16) return fail(c, OV_EINVAL, "nmass outside [1, 16]");
+    for (int i = 0; i < nmass; ++i)
+        if (!(mass[i] >= 0 && mass[i] < 2)) return fail(c, OV_EINVAL, "mass %d outside [0, 2)", i);
+    if (!(o->tol > 0) || o->maxiter < 1) return fail(c, OV_EINVAL, "need tol > 0 and maxiter >= 1");
+    if (o->adaptive && (o->min_order < 1 || o->min_order > c->npoly))
+        return fail(c, OV_EINVAL, "min_order outside [1, %d]", c->npoly);
+    if (o->inner_prec != OV_FP64 && o->inner_prec != OV_FP32) return fail(c, OV_EINVAL, "inner_prec must be FP64 or FP32");
+    std::vector<int> grp;
+    CHK(check_fields(c, nrhs, field_of_rhs, grp));
+    if (o->inner_prec == OV_FP32)
+        return api_mscg<float2>(c, nrhs, grp, nmass, mass, b_dev, x_dev, *o, report, relres);
+    return api_mscg<double2>(c, nrhs, grp, nmass, mass, b_dev, x_dev, *o, report, relres);
+}
+
+}  // extern "C"

@@ -56,6 +56,16 @@ class EigReport(C.Structure):
     _fields_ = [("iters", C.c_int), ("hw_applies", C.c_long), ("max_resid", C.c_double)]
 
 
+class MscgOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxiter", C.c_int), ("adaptive", C.c_int), ("min_order", C.c_int),
+                ("refine", C.c_int), ("inner_prec", C.c_int)]
+
+
+class MscgReport(C.Structure):
+    _fields_ = [("iters", C.c_int), ("sign_applies", C.c_long), ("dslash_applies", C.c_long),
+                ("refine_iters", C.c_int)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libov.so not found at {LIB_PATH}; build it with "
@@ -80,6 +90,7 @@ def _load():
         "ov_sign_backward": ([vp, i, vp, vp, vp, cp(d), vp, i], i),
         "ov_hw_eigensolve": ([vp, i, cp(EigOpts), vp, vp, cp(d), cp(d), i, cp(EigReport)], i),
         "ov_dense_heev": ([i, cp(d), cp(d), cp(d)], i),
+        "ov_multishift_cg": ([vp, i, cp(i), i, cp(d), vp, vp, cp(MscgOpts), cp(MscgReport), cp(d)], i),
         "ov_prof_enable": ([vp, i], i),
         "ov_prof_query": ([vp, C.c_char_p, cp(C.c_long), cp(d), cp(d)], i),
         "ov_set_tuning": ([vp, i, i, i], i),
@@ -106,7 +117,7 @@ EXPORTED = ("ov_create", "ov_destroy", "ov_set_stream", "ov_last_error", "ov_upl
             "ov_dov_apply", "ov_deflated_cg", "ov_sign_backward", "ov_prof_enable", "ov_prof_query",
             "ov_set_tuning", "ov_get_tuning", "ov_autotune", "ov_memory_used", "ov_set_graphs",
             "ov_set_site_order", "ov_set_occupancy", "ov_get_launch_config",
-            "ov_set_launch_config", "ov_hw_eigensolve", "ov_dense_heev")
+            "ov_set_launch_config", "ov_hw_eigensolve", "ov_dense_heev", "ov_multishift_cg")
 
 
 def _ints(v):
@@ -279,6 +290,26 @@ class Context:
                                        C.byref(ge) if want_eta else None,
                                        _dev(gx, (self.V, 4, 3), "gx") if want_x else None, int(ckpt_every)))
         return gU, (ge.value if want_eta else None), gx
+
+    def multishift_cg(self, b, masses, fields=None, tol=1e-10, maxiter=5000, adaptive=True, min_order=20,
+                      refine=True, inner_prec="fp64", raise_on_noconv=True):
+        """x[i] = D(masses[i])^{-1} b for chiral sources b (ov_multishift_cg).
+        Returns (x (nmass, nrhs, V, 4, 3), relres (nmass, nrhs), report)."""
+        b, n, fields = self._io(b, fields)
+        nm = len(masses)
+        x = torch.empty((nm,) + tuple(b.shape), dtype=torch.complex128, device=b.device)
+        rel = (C.c_double * (nm * n))()
+        rep = MscgReport()
+        opts = MscgOpts(float(tol), int(maxiter), int(bool(adaptive)), int(min_order), int(bool(refine)),
+                        PREC[inner_prec])
+        rc = lib.ov_multishift_cg(self._h, n, _ints(fields), nm, _doubles(masses), _dev(b, (self.V, 4, 3), "b"),
+                                  C.c_void_p(x.data_ptr()), C.byref(opts), C.byref(rep), rel)
+        if rc != OV_OK and not (rc == OV_ENOCONV and not raise_on_noconv):
+            self._chk(rc)
+        report = dict(iters=rep.iters, sign_applies=rep.sign_applies, dslash_applies=rep.dslash_applies,
+                      refine_iters=rep.refine_iters, status=rc)
+        import numpy as np
+        return x, np.array(list(rel)).reshape(nm, n), report
 
     def hw_eigensolve(self, field, l, k=None, cheb_order=60, cutoff=0.0, max_iter=20, tol=1e-10, prec="fp64",
                       x0=None, seed=0, install=True, want_vectors=True, raise_on_noconv=True):
