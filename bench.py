@@ -62,6 +62,9 @@ def parse():
     p.add_argument("--eig", action="store_true",
                    help="also time the H_w low-mode eigensolver at 24^3x48 (adds an 'eigensolver' object)")
     p.add_argument("--eig-l", type=int, default=LSMALL)
+    p.add_argument("--tts", action="store_true",
+                   help="also time propagators at 16^3x32: per-mass CG vs multi-mass sector CG")
+    p.add_argument("--tts-l", type=int, default=100)
     p.add_argument("--eig-order", type=int, default=100)
     p.add_argument("--eig-k", type=int, default=256)
     p.add_argument("--eig-maxiter", type=int, default=12)
@@ -175,6 +178,63 @@ def eig_measurement(torch, ov, U, args):
             "converged": rep["status"] == 0, "max_resid_rel": rep["max_resid"] / NORM,
             "lambda_min_abs": min(abs(v) for v in lam), "lambda_max_abs": max(abs(v) for v in lam),
             "kernels_ms": {c: round(v[1], 1) for c, v in prof.items()}}
+
+
+def tts_measurement(torch, ov, args):
+    """Time to solution at 16^3 x 32, one operator (q eta = 2/3 x 1e-3): H_w low modes by the
+    eigensolver, eps and n from lambda_l by eq. (2) for delta = 1e-10, then propagators of
+    4 point sources (both chiralities) for 3 masses to 1e-10, once by the per-mass deflated CG and
+    once by the multi-mass chirality-sector CG with adaptive order."""
+    import math
+
+    import synth
+
+    Lt = (16, 16, 16, 32)
+    U = synth.su3_links(Lt, 0.2, 2016)
+    ctx = ov.Context(Lt, BC, MW)
+    ctx.upload_gauge(torch.from_numpy(U).cuda())
+    ctx.set_fields([Q], [1e-3])
+    ctx.set_sign_params(100, 0.01, NORM)
+    l = args.tts_l
+    t0 = time.perf_counter()
+    lam, res, V, rep = ctx.hw_eigensolve(0, l, k=min(256, l + max(16, l // 4)), cheb_order=100, tol=1e-10,
+                                         prec="fp32", seed=3, install=True, want_vectors=False)
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    lam_l = max(abs(v) for v in lam)
+    eps = (0.95 * lam_l / NORM) ** 2
+    n = int(math.ceil(math.log(2 * 0.41 / 1e-10) / (2.1 * math.sqrt(eps))))
+    ctx.set_sign_params(n, eps, NORM)
+    src = synth.point_sources(Lt, (8, 0, 0, 16))[[0, 4, 7, 11]]
+    b = torch.from_numpy(src.copy()).cuda()
+    masses = (0.05, 0.1, 0.2)
+    print(f"[bench] tts: eigensolve {t_eig:.1f}s (|lambda_l| = {lam_l:.3f}), n = {n}, eps = {eps:.3e}",
+          file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_pm, rel_pm = 0, 0.0
+    for m in masses:
+        x, report = ctx.deflated_cg(b, mass=[m] * len(src), tol=1e-10)
+        it_pm += sum(r["iters"] for r in report)
+        rel_pm = max(rel_pm, max(r["relres"] for r in report))
+    torch.cuda.synchronize()
+    t_pm = time.perf_counter() - t0
+    print(f"[bench] tts: per-mass CG {t_pm:.1f}s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    x, rel, rep2 = ctx.multishift_cg(b, masses, tol=1e-10, adaptive=True, min_order=max(10, n // 10),
+                                     inner_prec="fp64", refine=True)
+    torch.cuda.synchronize()
+    t_ms = time.perf_counter() - t0
+    print(f"[bench] tts: multi-mass CG {t_ms:.1f}s", file=sys.stderr, flush=True)
+    ctx.close()
+    return {"workload": "16^3x32, q eta = 2/3 x 1e-3, 4 point sources x masses (0.05, 0.1, 0.2), tol 1e-10",
+            "eig_l": l, "eig_seconds": round(t_eig, 2), "eig_passes": rep["iters"], "lambda_l": lam_l,
+            "npoly": n, "eps": eps,
+            "per_mass_cg": {"seconds": round(t_pm, 2), "inner_iters_summed": it_pm, "max_relres": rel_pm},
+            "multi_mass_cg": {"seconds": round(t_ms, 2), "iters": rep2["iters"],
+                              "sign_applies": rep2["sign_applies"], "dslash_applies": rep2["dslash_applies"],
+                              "refine_inner_iters": rep2["refine_iters"], "max_relres": float(rel.max())},
+            "speedup": round(t_pm / t_ms, 2)}
 
 
 def cpu_baseline():
@@ -300,10 +360,13 @@ def main():
         "cpu_baseline": cpu,
     }
     ctx.close()
-    if args.eig:
+    if args.eig or args.tts:
         del x, y32
         torch.cuda.empty_cache()
+    if args.eig:
         line["eigensolver"] = eig_measurement(torch, ov, U, args)
+    if args.tts:
+        line["time_to_solution"] = tts_measurement(torch, ov, args)
     print(json.dumps(line), flush=True)
     if args.calibrate_copy:
         src = torch.empty(4 << 30, dtype=torch.uint8, device="cuda").fill_(1)

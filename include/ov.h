@@ -205,7 +205,8 @@ int ov_deflated_cg(ov_ctx *ctx, int nrhs, const int *field_of_rhs, const double 
  * law of eq. (2)) stays below 0.1 tol ||b|| / ||r|| (a less accurate operator
  * is enough while the residual is large), at least min_order; the context's
  * polynomial is restored afterwards.  The shifted solve runs in
- * opts->inner_prec (FP64, or FP32 down to max(tol, 1e-6)); then every x_i
+ * opts->inner_prec (FP64, or FP32 down to max(tol, 1e-5)) and stops early if
+ * its residual fails to halve within 200 iterations; then every x_i
  * gets its FP64 true residual ||b - D(m_i) x_i|| / ||b|| with the full
  * polynomial, and with opts->refine pairs above tol are finished by the
  * FP64-outer deflated CG of ov_deflated_cg, starting from x_i.

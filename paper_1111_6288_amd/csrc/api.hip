@@ -2308,7 +2308,11 @@ int api_mscg(ov_ctx *c, int nrhs, const std::vector<int> &grp, int nm, const dou
     const int n_full = guard.n;
     const std::vector<double> &coef_full = guard.coef;
     int cur_order = n_full;
-    const double inner_tol = (sizeof(S) == sizeof(double2)) ? o.tol : std::max(o.tol, 1e-6);
+    // an FP32 sector operator is accurate to ~1e-7, and a shifted CG cannot restart:
+    // FP32 stops at 1e-5 and leaves the rest to the refinement
+    const double inner_tol = (sizeof(S) == sizeof(double2)) ? o.tol : std::max(o.tol, 1e-5);
+    double window_rho = 1e300;   // stagnation watch: the residual must halve every 200 iterations
+    int window_start = 0;
     int it = 0;
     long sign_applies = 0, dslash_applies = 0;
     int rc = OV_OK;
@@ -2323,6 +2327,13 @@ int api_mscg(ov_ctx *c, int nrhs, const std::vector<int> &grp, int nm, const dou
                 if (!done[i * n + j]) rho = std::max(rho, res);
             }
         if (all) break;
+        if (it - window_start >= 200) {
+            if (!(rho < 0.5 * window_rho)) break;
+            window_rho = rho;
+            window_start = it;
+        } else if (it == 0) {
+            window_rho = rho;
+        }
         // 1. order of this application (relaxation: the operator may be less accurate
         //    as the residual falls)
         if (o.adaptive) {
