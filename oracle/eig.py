@@ -12,6 +12,10 @@ Hermitian operator H_w of the C oracle.
   Rayleigh-Ritz with H_w itself on the subspace found, which splits the
   pairs +lambda, -lambda that H_w^2 cannot tell apart.
 
+* ``dov_sector_low_modes_dense``: the lowest eigenpairs of D_ov^dag D_ov in
+  one chirality sector (the deflation basis, Sec. 2 end and Sec. 3.1), by
+  dense eigendecomposition of the sector block.
+
 Never imported by the product path.
 """
 from __future__ import annotations
@@ -68,3 +72,23 @@ def residuals(lat: api.Lattice, lam, vecs):
         r = api.dslash(lat, v, 1) - lj * v
         out.append(np.linalg.norm(r) / np.linalg.norm(v))
     return np.array(out)
+
+
+def dov_sector_low_modes_dense(S, chi, l):
+    """Lowest eigenpairs of D_ov^dag D_ov restricted to the chirality-chi sector (dense).
+
+    D_ov = 1 + gamma5 S with S a dense (approximate) sign matrix; the sector
+    holds the components with gamma5 = chi (spins 0, 1 for +1 in the chiral
+    basis).  Returns (lambda[l] ascending, W (l, V, 4, 3) with zeros in the
+    other sector).
+    """
+    n = S.shape[0]
+    V = n // 12
+    g5 = np.diag(dense.gamma5_full(V)).real
+    D = np.eye(n) + dense.gamma5_full(V) @ S
+    A = D.conj().T @ D
+    idx = np.nonzero(g5 == chi)[0]
+    w, v = np.linalg.eigh(A[np.ix_(idx, idx)])
+    W = np.zeros((l, n), np.complex128)
+    W[:, idx] = v[:, :l].T
+    return w[:l], W.reshape(l, V, 4, 3)
