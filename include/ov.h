@@ -245,7 +245,7 @@ int ov_multishift_cg(ov_ctx *ctx, int nrhs, const int *field_of_rhs, int nmass, 
  *      that damps [a, norm^2] (scaled recurrence, normalised at the lowest
  *      Ritz value of H_w^2; 2m H_w applications per vector).  opts->prec
  *      OV_FP64: FP64 filter; OV_FP32: FP32 filter until the wanted residuals
- *      are below 1e-6 * norm, FP64 filter after that;
+ *      are below 1e-6 * norm or fall less than 3x in a pass, FP64 after that;
  *   2. orthonormalises it in FP64 (shifted Cholesky QR, then two plain
  *      Cholesky QR passes; Gram matrices on the matrix cores);
  *   3. Rayleigh-Ritz on its span (FP64) with H_w^2, whose wanted values are
@@ -283,6 +283,24 @@ typedef struct {
 
 int ov_hw_eigensolve(ov_ctx *ctx, int field, const ov_eig_opts *opts, const void *X0_dev, void *V_dev,
                      double *lambda, double *resid, int install, ov_eig_report *report);
+
+/*
+ * Low modes of D_ov for deflation (Sec. 3.1: eigensystem of D_ov with
+ * Chebyshev acceleration of order 12; Sec. 2 end: deflation).  D_ov^dag D_ov
+ * commutes with gamma5 and equals A = 2 + 2 P s P on the sector
+ * P = (1 + chi gamma5)/2 (s^2 = 1), a Hermitian operator with spectrum in
+ * [0, 4] whose wanted eigenvalues are the smallest.  The same filtered
+ * subspace iteration as ov_hw_eigensolve runs on A in the sector chirality
+ * = +1 or -1 (one sign application per filter degree and vector; the filter
+ * damps [a, 4], first a = opts->cutoff, default 0.1), with Rayleigh-Ritz on
+ * A; residuals ||A w - lambda w|| <= tol * 4.  lambda[l] are eigenvalues of
+ * D_ov^dag D_ov (= |eigenvalue of D_ov|^2), ascending.  W_dev [l][V][4][3]
+ * complex128 (needed when install != 0, which makes the basis the field
+ * group's deflation basis as by ov_upload_deflation).  report->hw_applies
+ * counts sign applications here.  Synchronises.
+ */
+int ov_dov_eigensolve(ov_ctx *ctx, int field, int chirality, const ov_eig_opts *opts, const void *X0_dev,
+                      void *W_dev, double *lambda, double *resid, int install, ov_eig_report *report);
 
 /*
  * Host utility (no context, no GPU): eigen-decomposition of a Hermitian

@@ -2009,7 +2009,7 @@ int install_small(ov_ctx *c, int field, int l, const double2 *Vplanes, const dou
 }
 
 // FP32 filter (o.prec == OV_FP32) while the wanted residuals exceed
-// kFp32Floor * norm, FP64 filter afterwards.
+// kFp32Floor * norm and fall at least 3x per pass, FP64 filter afterwards.
 constexpr double kFp32Floor = 1e-6;
 
 int api_eigensolve(ov_ctx *c, int field, const ov_eig_opts &o, const void *X0, void *V_out, double *lambda,
@@ -2038,6 +2038,7 @@ int api_eigensolve(ov_ctx *c, int field, const ov_eig_opts &o, const void *X0, v
         for (auto &p : FS) p = ws_take<S>(c, fe * k);
     if (!w.r2 || (has32 && !FS[3])) return fail(c, OV_ENOMEM, "workspace too small (internal)");
     bool use32 = has32;   // switched off once the FP32 floor is reached
+    double rmax_prev = 1e300;
 
     std::vector<int> grp(k, field);
     Batch b;
@@ -2160,7 +2161,9 @@ int api_eigensolve(ov_ctx *c, int field, const ov_eig_opts &o, const void *X0, v
             conv = conv && std::isfinite(r[j]) && r[j] <= o.tol * c->norm;
             rmax = std::max(rmax, r[j]);
         }
-        if (use32 && rmax <= kFp32Floor * c->norm) use32 = false;
+        // hand over to FP64 at the FP32 floor, or as soon as FP32 stops making progress
+        if (use32 && (rmax <= kFp32Floor * c->norm || rmax > 0.3 * rmax_prev)) use32 = false;
+        rmax_prev = rmax;
         for (int j = 0; j < k; ++j)
             if (!std::isfinite(th[j]) || !std::isfinite(r[j])) return fail(c, OV_ENAN, "eigensolver: non-finite Ritz pair");
         if (conv) break;
@@ -2530,6 +2533,219 @@ int ov_multishift_cg(ov_ctx *c, int nrhs, const int *field_of_rhs, int nmass, co
     if (o->inner_prec == OV_FP32)
         return api_mscg<float2>(c, nrhs, grp, nmass, mass, b_dev, x_dev, *o, report, relres);
     return api_mscg<double2>(c, nrhs, grp, nmass, mass, b_dev, x_dev, *o, report, relres);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- D_ov low modes (deflation basis)
+namespace {
+
+// Y = alpha A X + beta X + gamma Z on the chirality-chi sector, A X = 2 X + chi s X + gamma5 s X;
+// U receives s X.  Y must not alias X, U or Z.
+template <class S>
+int sector_apply(ov_ctx *c, const Batch &b, const int *fg, double chi, const S *X, S *Y, S *U, SignBufs<S> &sb,
+                 double alpha, double beta, const S *Z, double gamma)
+{
+    CHK(sign_batch<S>(c, b, fg, X, U, sb));
+    {
+        const S *in[3] = {X, U, Z};
+        const double2 cc[3] = {make_double2(2.0 * alpha + beta, 0), make_double2(alpha * chi, 0), make_double2(gamma, 0)};
+        CHK((lincomb<S, S>(c, b, Y, Z ? 3 : 2, in, nullptr, cc, 0)));
+    }
+    const S *in2[2] = {Y, U};
+    const double2 cc2[2] = {make_double2(1, 0), make_double2(alpha, 0)};
+    return lincomb<S, S>(c, b, Y, 2, in2, nullptr, cc2, 2);
+}
+
+int api_dov_eigensolve(ov_ctx *c, int field, int chirality, const ov_eig_opts &o, const void *X0, void *W_out,
+                       double *lambda, double *resid, ov_eig_report *rep)
+{
+    using S = float2;
+    const int k = o.k, l = o.l;
+    const double chi = chirality > 0 ? 1.0 : -1.0;
+    const long fe = (long)field_elems(c);
+    const long K = 12L * c->g.Vp;
+    const long nchunk = (K + proj_dot_chunk(K) - 1) / proj_dot_chunk(K);
+    const bool has32 = o.prec == OV_FP32;
+    size_t need = 5 * align_up(field_bytes<double2>(c) * k) + sign_bufs_bytes<double2>(c, k) +
+                  2 * align_up(16ul * k * k) + align_up((size_t)nchunk * 48 * 256 * 16) + align_up(16ul * k) +
+                  2 * align_up(8ul * (8192 + k));
+    if (has32) need += 5 * align_up(field_bytes<S>(c) * k) + sign_bufs_bytes<S>(c, k);
+    CHK(ws_reserve(c, need));
+    EigBufs w;
+    for (auto &p : w.B) p = ws_take<double2>(c, fe * k);
+    double2 *U64 = ws_take<double2>(c, fe * k);
+    w.G = ws_take<double2>(c, (size_t)k * k);
+    w.E = ws_take<double2>(c, (size_t)k * k);
+    w.part = ws_take<double2>(c, (size_t)nchunk * 48 * 256);
+    w.coef = ws_take<double2>(c, k);
+    w.red = ws_take<double>(c, 8192 + k);
+    w.r2 = ws_take<double>(c, 8192 + k);
+    SignBufs<double2> sb64;
+    CHK(take_sign_bufs<double2>(c, k, sb64));
+    S *FS[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    SignBufs<S> sb32;
+    if (has32) {
+        for (auto &p : FS) p = ws_take<S>(c, fe * k);
+        CHK(take_sign_bufs<S>(c, k, sb32));
+    }
+    if (!w.r2 || !U64 || (has32 && !FS[4])) return fail(c, OV_ENOMEM, "workspace too small (internal)");
+    bool use32 = has32;
+    double rmax_prev = 1e300;
+
+    std::vector<int> grp(k, field);
+    Batch b;
+    CHK(make_batch(c, iota_vec(k), grp, b));
+    const int *fg = dev_ints(c, grp);
+    const double bnd = 4.0;   // spectrum of 2 + 2 P s P for |s| <= 1
+    double a = o.cutoff > 0 ? o.cutoff : 0.1;
+    double lref = 0.0;
+    auto project = [&](double2 *Y) -> int {   // Y = (Y + chi gamma5 Y) / 2
+        const double2 *in[2] = {Y, Y};
+        const double2 cc[2] = {make_double2(0.5, 0), make_double2(0.5 * chi, 0)};
+        return lincomb<double2, double2>(c, b, Y, 2, in, nullptr, cc, 2);
+    };
+    HIPCHK(launch_pack_spinor<double2>((const double2 *)X0, w.B[0], fe, nullptr, k, c->g.V, c->g.Vp, c->stream));
+    CHK(project(w.B[0]));
+    int ix = 0;
+    std::vector<double> th(k), r(k);
+    int it = 0;
+    long applies = 0;
+    bool conv = false;
+    while (it < o.max_iter) {
+        ++it;
+        if (a >= bnd) a = 0.5 * bnd;
+        const double e = 0.5 * (bnd - a), cc = 0.5 * (bnd + a);
+        double sigma = e / (lref - cc);
+        const double tau = 2.0 / sigma;
+        const int m = o.cheb_order;
+        int iy;
+        if (!use32) {
+            // F = three of the FP64 blocks (the first holds X), T-slot = U64
+            int q[4], nq = 0;
+            q[nq++] = ix;
+            for (int t = 0; t < 4; ++t)
+                if (t != ix) q[nq++] = t;
+            double2 *F[3] = {w.B[q[0]], w.B[q[1]], w.B[q[2]]};
+            CHK(sector_apply<double2>(c, b, fg, chi, F[0], F[1], U64, sb64, sigma / e, -(sigma / e) * cc, nullptr, 0.0));
+            int i0 = 0, i1 = 1;
+            for (int j = 2; j <= m; ++j) {
+                const double sn = 1.0 / (tau - sigma);
+                const int i2 = 3 - i0 - i1;
+                CHK(sector_apply<double2>(c, b, fg, chi, F[i1], F[i2], U64, sb64, 2.0 * sn / e, -2.0 * sn / e * cc,
+                                          F[i0], -sigma * sn));
+                sigma = sn;
+                i0 = i1;
+                i1 = i2;
+            }
+            iy = q[m >= 1 ? i1 : 0];
+        } else {
+            S *F[3] = {FS[0], FS[1], FS[2]};
+            CHK((copy_fields<double2, S>(c, b, w.B[ix], FS[0])));
+            CHK(sector_apply<S>(c, b, fg, chi, F[0], F[1], FS[3], sb32, sigma / e, -(sigma / e) * cc, nullptr, 0.0));
+            int i0 = 0, i1 = 1;
+            for (int j = 2; j <= m; ++j) {
+                const double sn = 1.0 / (tau - sigma);
+                const int i2 = 3 - i0 - i1;
+                CHK(sector_apply<S>(c, b, fg, chi, F[i1], F[i2], FS[3], sb32, 2.0 * sn / e, -2.0 * sn / e * cc, F[i0],
+                                    -sigma * sn));
+                sigma = sn;
+                i0 = i1;
+                i1 = i2;
+            }
+            iy = (ix + 1) % 4;
+            CHK((copy_fields<S, double2>(c, b, F[m >= 1 ? i1 : 0], w.B[iy])));
+        }
+        applies += (long)m * k;
+        CHK(project(w.B[iy]));
+        // orthonormalise
+        const int iq = (iy + 1) % 4;
+        CHK(cholqr_pass(c, w.B[iy], w.B[iq], k, true, w.G, w.E, w.part));
+        CHK(cholqr_pass(c, w.B[iq], w.B[iy], k, false, w.G, w.E, w.part));
+        CHK(cholqr_pass(c, w.B[iy], w.B[iq], k, false, w.G, w.E, w.part));
+        // Rayleigh-Ritz with A (its wanted values are the smallest: no interior problem)
+        const int ih = (iq + 1) % 4, ixn = (iq + 2) % 4, it2 = (iq + 3) % 4;
+        CHK(sector_apply<double2>(c, b, fg, chi, w.B[iq], w.B[ih], U64, sb64, 1.0, 0.0, nullptr, 0.0));
+        applies += k;
+        std::vector<cd> Hs, Z((size_t)k * k);
+        CHK(block_gram(c, w.B[iq], k, w.B[ih], k, w.G, w.part));
+        CHK(fetch_square(c, w.G, k, Hs));
+        ov::heev_jacobi(k, Hs.data(), th.data(), Z.data());
+        CHK(put_square(c, Z, w.E));
+        CHK(block_rotate(c, w.B[iq], k, w.E, k, w.B[ixn]));
+        CHK(block_rotate(c, w.B[ih], k, w.E, k, w.B[it2]));
+        {
+            std::vector<double2> cf(k);
+            for (int j = 0; j < k; ++j) cf[j] = make_double2(-th[j], 0.0);
+            HIPCHK(h2d(c, w.coef, cf.data(), 16ul * k));
+            const double2 *in[2] = {w.B[it2], w.B[ixn]};
+            const double2 *cfs[2] = {nullptr, w.coef};
+            int nb = 0;
+            CHK((lincomb<double2, double2>(c, b, w.B[iq], 2, in, cfs, nullptr, 0, w.red, &nb)));
+            HIPCHK(launch_reduce_r(w.red, nb, k, w.r2, nullptr, c->stream));
+            HIPCHK(hipMemcpyAsync(r.data(), w.r2, 8ul * k, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            for (auto &v : r) v = std::sqrt(std::max(v, 0.0));
+        }
+        ix = ixn;
+        conv = true;
+        double rmax = 0;
+        for (int j = 0; j < l; ++j) {
+            conv = conv && std::isfinite(r[j]) && r[j] <= o.tol * bnd;
+            rmax = std::max(rmax, r[j]);
+        }
+        for (int j = 0; j < k; ++j)
+            if (!std::isfinite(th[j]) || !std::isfinite(r[j])) return fail(c, OV_ENAN, "eigensolver: non-finite Ritz pair");
+        if (use32 && (rmax <= kFp32Floor * bnd || rmax > 0.3 * rmax_prev)) use32 = false;
+        rmax_prev = rmax;
+        if (conv) break;
+        a = th[k - 1];
+        lref = std::max(th[0], 0.0);
+        if (!(a > lref)) a = lref + 1e-3 * bnd;
+    }
+    for (int j = 0; j < l; ++j) {
+        lambda[j] = th[j];
+        if (resid) resid[j] = r[j];
+    }
+    if (W_out)
+        HIPCHK(launch_unpack_spinor<double2>(w.B[ix], (double2 *)W_out, fe, nullptr, l, c->g.V, c->g.Vp, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (rep) {
+        rep->iters = it;
+        rep->hw_applies = applies;   // sign applications here
+        double mr = 0;
+        for (int j = 0; j < l; ++j) mr = std::max(mr, r[j]);
+        rep->max_resid = mr;
+    }
+    if (!conv) return fail(c, OV_ENOCONV, "D_ov eigensolver: %d lowest pairs not converged to %.2e in %d passes", l,
+                           o.tol, it);
+    return OV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ov_dov_eigensolve(ov_ctx *c, int field, int chirality, const ov_eig_opts *o, const void *X0_dev, void *W_dev,
+                      double *lambda, double *resid, int install, ov_eig_report *report)
+{
+    CHK(check_ctx(c));
+    if (!o || !X0_dev || !lambda) return fail(c, OV_EINVAL, "null options, start block or lambda");
+    if (install && !W_dev) return fail(c, OV_EINVAL, "install needs the output basis W_dev");
+    if (chirality != 1 && chirality != -1) return fail(c, OV_EINVAL, "chirality must be +1 or -1");
+    if (field < 0 || field >= c->nfield) return fail(c, OV_EINVAL, "field %d outside [0, %d)", field, c->nfield);
+    if (!c->have_gauge) return fail(c, OV_ESTATE, "no gauge field uploaded");
+    if (!c->have_sign) return fail(c, OV_ESTATE, "sign parameters not set");
+    if (o->k < 1 || o->k > 256 || o->l < 1 || o->l > o->k)
+        return fail(c, OV_EINVAL, "need 1 <= l <= k <= 256 (l = %d, k = %d)", o->l, o->k);
+    if (o->cheb_order < 1 || o->cheb_order > 10000) return fail(c, OV_EINVAL, "cheb_order outside [1, 10000]");
+    if (o->max_iter < 1) return fail(c, OV_EINVAL, "max_iter must be >= 1");
+    if (!(o->tol > 0)) return fail(c, OV_EINVAL, "tol must be positive");
+    if (o->prec != OV_FP64 && o->prec != OV_FP32) return fail(c, OV_EINVAL, "filter precision must be FP64 or FP32");
+    const int rc = api_dov_eigensolve(c, field, chirality, *o, X0_dev, W_dev, lambda, resid, report);
+    if (rc != OV_OK && rc != OV_ENOCONV) return rc;
+    if (install) CHK(ov_upload_deflation(c, field, o->l, W_dev));
+    return rc == OV_OK ? OV_OK : fail(c, OV_ENOCONV, "D_ov eigensolver did not converge (basis installed anyway)");
 }
 
 }  // extern "C"

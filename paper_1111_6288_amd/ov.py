@@ -91,6 +91,7 @@ def _load():
         "ov_hw_eigensolve": ([vp, i, cp(EigOpts), vp, vp, cp(d), cp(d), i, cp(EigReport)], i),
         "ov_dense_heev": ([i, cp(d), cp(d), cp(d)], i),
         "ov_multishift_cg": ([vp, i, cp(i), i, cp(d), vp, vp, cp(MscgOpts), cp(MscgReport), cp(d)], i),
+        "ov_dov_eigensolve": ([vp, i, i, cp(EigOpts), vp, vp, cp(d), cp(d), i, cp(EigReport)], i),
         "ov_prof_enable": ([vp, i], i),
         "ov_prof_query": ([vp, C.c_char_p, cp(C.c_long), cp(d), cp(d)], i),
         "ov_set_tuning": ([vp, i, i, i], i),
@@ -117,7 +118,8 @@ EXPORTED = ("ov_create", "ov_destroy", "ov_set_stream", "ov_last_error", "ov_upl
             "ov_dov_apply", "ov_deflated_cg", "ov_sign_backward", "ov_prof_enable", "ov_prof_query",
             "ov_set_tuning", "ov_get_tuning", "ov_autotune", "ov_memory_used", "ov_set_graphs",
             "ov_set_site_order", "ov_set_occupancy", "ov_get_launch_config",
-            "ov_set_launch_config", "ov_hw_eigensolve", "ov_dense_heev", "ov_multishift_cg")
+            "ov_set_launch_config", "ov_hw_eigensolve", "ov_dense_heev", "ov_multishift_cg",
+            "ov_dov_eigensolve")
 
 
 def _ints(v):
@@ -310,6 +312,30 @@ class Context:
                       refine_iters=rep.refine_iters, status=rc)
         import numpy as np
         return x, np.array(list(rel)).reshape(nm, n), report
+
+    def dov_eigensolve(self, field, chirality, l, k=None, cheb_order=12, cutoff=0.0, max_iter=30, tol=1e-10,
+                       prec="fp64", x0=None, seed=0, install=False, raise_on_noconv=True):
+        """Lowest eigenpairs of D_ov^dag D_ov in one chirality sector (ov_dov_eigensolve).
+        Returns (lambda, resid, W (l, V, 4, 3), report)."""
+        k = int(k if k is not None else l + max(4, l // 4))
+        if x0 is None:
+            dev = f"cuda:{self.device}"
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(int(seed))
+            x0 = torch.randn((k, self.V, 4, 3), dtype=torch.complex128, device=dev, generator=gen)
+        x0 = x0.reshape(k, self.V, 4, 3).contiguous()
+        W = torch.empty((l, self.V, 4, 3), dtype=torch.complex128, device=x0.device)
+        lam = (C.c_double * l)()
+        res = (C.c_double * l)()
+        rep = EigReport()
+        opts = EigOpts(int(l), k, int(cheb_order), float(cutoff), int(max_iter), float(tol), PREC[prec])
+        rc = lib.ov_dov_eigensolve(self._h, int(field), int(chirality), C.byref(opts),
+                                   _dev(x0, (self.V, 4, 3), "x0"), _dev(W, (self.V, 4, 3), "W"), lam, res,
+                                   int(bool(install)), C.byref(rep))
+        if rc != OV_OK and not (rc == OV_ENOCONV and not raise_on_noconv):
+            self._chk(rc)
+        report = dict(iters=rep.iters, sign_applies=rep.hw_applies, max_resid=rep.max_resid, status=rc)
+        return list(lam), list(res), W, report
 
     def hw_eigensolve(self, field, l, k=None, cheb_order=60, cutoff=0.0, max_iter=20, tol=1e-10, prec="fp64",
                       x0=None, seed=0, install=True, want_vectors=True, raise_on_noconv=True):
