@@ -65,6 +65,7 @@ def parse():
     p.add_argument("--tts", action="store_true",
                    help="also time propagators at 16^3x32: per-mass CG vs multi-mass sector CG")
     p.add_argument("--tts-l", type=int, default=100)
+    p.add_argument("--tts-ldov", type=int, default=16)
     p.add_argument("--eig-order", type=int, default=100)
     p.add_argument("--eig-k", type=int, default=256)
     p.add_argument("--eig-maxiter", type=int, default=12)
@@ -210,31 +211,64 @@ def tts_measurement(torch, ov, args):
     masses = (0.05, 0.1, 0.2)
     print(f"[bench] tts: eigensolve {t_eig:.1f}s (|lambda_l| = {lam_l:.3f}), n = {n}, eps = {eps:.3e}",
           file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    it_pm, rel_pm = 0, 0.0
-    for m in masses:
-        x, report = ctx.deflated_cg(b, mass=[m] * len(src), tol=1e-10)
-        it_pm += sum(r["iters"] for r in report)
-        rel_pm = max(rel_pm, max(r["relres"] for r in report))
-    torch.cuda.synchronize()
-    t_pm = time.perf_counter() - t0
+    def per_mass(deflate):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it_pm, rel_pm = 0, 0.0
+        for m in masses:
+            x, report = ctx.deflated_cg(b, mass=[m] * len(src), tol=1e-10, use_deflation=deflate)
+            it_pm += sum(r["iters"] for r in report)
+            rel_pm = max(rel_pm, max(r["relres"] for r in report))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, it_pm, rel_pm
+
+    t_pm, it_pm, rel_pm = per_mass(False)
     print(f"[bench] tts: per-mass CG {t_pm:.1f}s", file=sys.stderr, flush=True)
+    # D_ov low modes in both chirality sectors -> deflation basis
+    ld = args.tts_ldov
     t0 = time.perf_counter()
-    x, rel, rep2 = ctx.multishift_cg(b, masses, tol=1e-10, adaptive=True, min_order=max(10, n // 10),
-                                     inner_prec="fp64", refine=True)
+    # a deflation basis needs no 1e-10 eigenvectors: the outer FP64 loop absorbs the rest
+    lam_p, _, Wp, rp = ctx.dov_eigensolve(0, 1, ld, k=ld + 8, cheb_order=24, tol=1e-6, prec="fp32", seed=5,
+                                          max_iter=20, raise_on_noconv=False)
+    print(f"[bench] tts: D_ov modes, + sector: {rp['iters']} passes, {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    lam_m, _, Wm, rm = ctx.dov_eigensolve(0, -1, ld, k=ld + 8, cheb_order=24, tol=1e-6, prec="fp32", seed=6,
+                                          max_iter=20, raise_on_noconv=False)
+    ctx.upload_deflation(0, torch.cat([Wp, Wm]))
+    del Wp, Wm
     torch.cuda.synchronize()
-    t_ms = time.perf_counter() - t0
-    print(f"[bench] tts: multi-mass CG {t_ms:.1f}s", file=sys.stderr, flush=True)
+    t_deig = time.perf_counter() - t0
+    print(f"[bench] tts: D_ov eigensolve 2 x {ld} modes {t_deig:.1f}s", file=sys.stderr, flush=True)
+    t_pmd, it_pmd, rel_pmd = per_mass(True)
+    print(f"[bench] tts: deflated per-mass CG {t_pmd:.1f}s", file=sys.stderr, flush=True)
+    mres = {}
+    for adaptive in (False, True):
+        t0 = time.perf_counter()
+        x, rel, rep2 = ctx.multishift_cg(b, masses, tol=1e-10, adaptive=adaptive, min_order=max(10, n // 10),
+                                         inner_prec="fp64", refine=True)
+        torch.cuda.synchronize()
+        t_ms = time.perf_counter() - t0
+        mres[adaptive] = (t_ms, rel, rep2)
+        print(f"[bench] tts: multi-mass CG (adaptive={adaptive}) {t_ms:.1f}s", file=sys.stderr, flush=True)
     ctx.close()
+    t_ms, rel, rep2 = mres[True]
     return {"workload": "16^3x32, q eta = 2/3 x 1e-3, 4 point sources x masses (0.05, 0.1, 0.2), tol 1e-10",
             "eig_l": l, "eig_seconds": round(t_eig, 2), "eig_passes": rep["iters"], "lambda_l": lam_l,
             "npoly": n, "eps": eps,
             "per_mass_cg": {"seconds": round(t_pm, 2), "inner_iters_summed": it_pm, "max_relres": rel_pm},
+            "dov_eig": {"modes_per_sector": ld, "seconds": round(t_deig, 2), "passes": [rp["iters"], rm["iters"]],
+                        "tol": 1e-6, "max_resid": max(rp["max_resid"], rm["max_resid"]),
+                        "lambda_min": min(lam_p[0], lam_m[0]), "lambda_max": max(lam_p[-1], lam_m[-1])},
+            "deflated_per_mass_cg": {"seconds": round(t_pmd, 2), "inner_iters_summed": it_pmd,
+                                     "max_relres": rel_pmd},
             "multi_mass_cg": {"seconds": round(t_ms, 2), "iters": rep2["iters"],
                               "sign_applies": rep2["sign_applies"], "dslash_applies": rep2["dslash_applies"],
                               "refine_inner_iters": rep2["refine_iters"], "max_relres": float(rel.max())},
-            "speedup": round(t_pm / t_ms, 2)}
+            "multi_mass_cg_fixed_order": {"seconds": round(mres[False][0], 2),
+                                          "dslash_applies": mres[False][2]["dslash_applies"],
+                                          "refine_inner_iters": mres[False][2]["refine_iters"]},
+            "speedup_multi_mass_vs_per_mass": round(t_pm / t_ms, 2),
+            "speedup_deflation": round(t_pm / t_pmd, 2)}
 
 
 def cpu_baseline():

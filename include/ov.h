@@ -303,6 +303,17 @@ int ov_dov_eigensolve(ov_ctx *ctx, int field, int chirality, const ov_eig_opts *
                       void *W_dev, double *lambda, double *resid, int install, ov_eig_report *report);
 
 /*
+ * Time-slice norms for the pion correlator (Sec. 4: G_E(t), G_0(t) and
+ * R(t) = G_E(t) / G_0(t)): out[j][t] = sum over the sites of time slice t
+ * and the 12 spin-colour components of |x_j|^2, for nrhs canonical
+ * complex128 fields x_dev [nrhs][V][4][3].  With gamma5-hermiticity the
+ * connected pseudoscalar correlator of one flavour from the 12 point-source
+ * propagators S_j is G(t) = sum_j out[j][t].  Fixed-order (deterministic)
+ * reduction.  out: host [nrhs][Lt].  Synchronises.
+ */
+int ov_timeslice_norm2(ov_ctx *ctx, int nrhs, const void *x_dev, double *out);
+
+/*
  * Host utility (no context, no GPU): eigen-decomposition of a Hermitian
  * n x n matrix by cyclic Jacobi rotations, as the eigensolver's
  * Rayleigh-Ritz step uses it.  A: column-major complex (interleaved re, im),

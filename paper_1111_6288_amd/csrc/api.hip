@@ -2749,3 +2749,25 @@ int ov_dov_eigensolve(ov_ctx *c, int field, int chirality, const ov_eig_opts *o,
 }
 
 }  // extern "C"
+
+extern "C" {
+
+int ov_timeslice_norm2(ov_ctx *c, int nrhs, const void *x_dev, double *out)
+{
+    CHK(check_ctx(c));
+    if (nrhs < 0 || nrhs > 65535) return fail(c, OV_EINVAL, "nrhs outside [0, 65535]");
+    if (nrhs == 0) return OV_OK;
+    if (!x_dev || !out) return fail(c, OV_EINVAL, "null argument");
+    const int Lxyz = c->g.Lxyz, Lt = c->g.Lt;
+    const int nb = slice_norm2_blocks(Lxyz);
+    const size_t m = (size_t)nrhs * Lt;
+    CHK(ws_reserve(c, align_up(8 * m * nb) + align_up(8 * m)));
+    double *part = ws_take<double>(c, m * nb), *o = ws_take<double>(c, m);
+    if (!o) return fail(c, OV_ENOMEM, "workspace too small (internal)");
+    HIPCHK(launch_slice_norm2((const double2 *)x_dev, nrhs, c->g.V, Lxyz, Lt, part, o, c->stream));
+    HIPCHK(hipMemcpyAsync(out, o, 8 * m, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return OV_OK;
+}
+
+}  // extern "C"

@@ -3,6 +3,8 @@
 // batched inner products with a fixed-order two-stage reduction, and the
 // per-RHS CG scalar updates.  All of them are HBM-bound; they read and write
 // whole planes with consecutive lanes on consecutive sites.
+#include <algorithm>
+
 #include "ov_device.h"
 #include "ov_internal.h"
 
@@ -62,6 +64,40 @@ __global__ void k_pack_links(const double2 *__restrict__ in, S *__restrict__ out
         }
         stc<double>(out, lpos<S>(mu, k, site, Vp), v);
     }
+}
+
+// ---------------------------------------------------------------- time-slice norms
+// part[(j Lt + t) nb + blk] = sum over the sites of block blk of time slice t
+// of sum_k |x_j(site, k)|^2, canonical complex128 input [n][V][12] (t is the
+// slowest site index, so a time slice is Lxyz consecutive sites).
+__global__ __launch_bounds__(256) void k_slice_norm2(const double2 *__restrict__ x, long V, int Lxyz, int Lt,
+                                                     int nb, double *__restrict__ part)
+{
+    const int blk = blockIdx.x, t = blockIdx.y, j = blockIdx.z;
+    double s = 0.0;
+    for (int o = blk * blockDim.x + threadIdx.x; o < Lxyz; o += nb * blockDim.x) {
+        const double2 *p = x + ((long)j * V + (long)t * Lxyz + o) * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) s += p[k].x * p[k].x + p[k].y * p[k].y;
+    }
+    __shared__ double sh[256];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[((long)j * Lt + t) * nb + blk] = sh[0];
+}
+
+// out[j Lt + t] = sum_blk part[(j Lt + t) nb + blk]  (fixed order)
+__global__ void k_slice_finish(const double *__restrict__ part, int nb, int m, double *__restrict__ out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(long)e * nb + b];
+    out[e] = s;
 }
 
 // Count of non-finite doubles in a buffer (result accumulated atomically).
@@ -270,6 +306,19 @@ hipError_t launch_pack_links(const double2 *in, S *out, int V, int Vp, hipStream
 {
     dim3 grid((Vp + 255) / 256, 4);
     hipLaunchKernelGGL((k_pack_links<S>), grid, dim3(256), 0, st, in, out, V, Vp);
+    return hipGetLastError();
+}
+
+int slice_norm2_blocks(int Lxyz) { return std::max(1, std::min(64, (Lxyz + 255) / 256)); }
+
+hipError_t launch_slice_norm2(const double2 *x, int n, long V, int Lxyz, int Lt, double *part, double *out,
+                              hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int nb = slice_norm2_blocks(Lxyz);
+    hipLaunchKernelGGL(k_slice_norm2, dim3(nb, Lt, n), dim3(256), 0, st, x, V, Lxyz, Lt, nb, part);
+    const int m = n * Lt;
+    hipLaunchKernelGGL(k_slice_finish, dim3((m + 255) / 256), dim3(256), 0, st, part, nb, m, out);
     return hipGetLastError();
 }
 

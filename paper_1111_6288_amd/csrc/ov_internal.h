@@ -98,6 +98,9 @@ struct ForceArgs {
     Geo g;
 };
 hipError_t launch_force(const ForceArgs &a, hipStream_t st);
+int slice_norm2_blocks(int Lxyz);
+hipError_t launch_slice_norm2(const double2 *x, int n, long V, int Lxyz, int Lt, double *part, double *out,
+                              hipStream_t st);
 hipError_t launch_force_finish(const double2 *G, const double2 *U, const cx<double> *phase_row, double q,
                                Geo g, double2 *gU_canon, double *eta_part, int nb, hipStream_t st);
 

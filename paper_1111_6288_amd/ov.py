@@ -92,6 +92,7 @@ def _load():
         "ov_dense_heev": ([i, cp(d), cp(d), cp(d)], i),
         "ov_multishift_cg": ([vp, i, cp(i), i, cp(d), vp, vp, cp(MscgOpts), cp(MscgReport), cp(d)], i),
         "ov_dov_eigensolve": ([vp, i, i, cp(EigOpts), vp, vp, cp(d), cp(d), i, cp(EigReport)], i),
+        "ov_timeslice_norm2": ([vp, i, vp, cp(d)], i),
         "ov_prof_enable": ([vp, i], i),
         "ov_prof_query": ([vp, C.c_char_p, cp(C.c_long), cp(d), cp(d)], i),
         "ov_set_tuning": ([vp, i, i, i], i),
@@ -119,7 +120,7 @@ EXPORTED = ("ov_create", "ov_destroy", "ov_set_stream", "ov_last_error", "ov_upl
             "ov_set_tuning", "ov_get_tuning", "ov_autotune", "ov_memory_used", "ov_set_graphs",
             "ov_set_site_order", "ov_set_occupancy", "ov_get_launch_config",
             "ov_set_launch_config", "ov_hw_eigensolve", "ov_dense_heev", "ov_multishift_cg",
-            "ov_dov_eigensolve")
+            "ov_dov_eigensolve", "ov_timeslice_norm2")
 
 
 def _ints(v):
@@ -158,6 +159,13 @@ def dense_heev(A):
     if rc != 0:
         raise ValueError("ov_dense_heev: bad argument")
     return w, Z.view(np.complex128).reshape(n, n).T.copy()
+
+
+def ratio_R(G_E, G_0):
+    """R(t) = G_E(t) / G_0(t) (Sec. 4): G_E from the field runs (average of u and d at +E and -E),
+    G_0 without field."""
+    import numpy as np
+    return np.asarray(G_E, dtype=float) / np.asarray(G_0, dtype=float)
 
 
 class Context:
@@ -336,6 +344,21 @@ class Context:
             self._chk(rc)
         report = dict(iters=rep.iters, sign_applies=rep.hw_applies, max_resid=rep.max_resid, status=rc)
         return list(lam), list(res), W, report
+
+    def timeslice_norm2(self, x):
+        """out[j, t] = sum over time slice t of |x_j|^2 (ov_timeslice_norm2); numpy (nrhs, Lt)."""
+        import numpy as np
+        x = x.reshape(-1, self.V, 4, 3).contiguous()
+        n = int(x.shape[0])
+        out = np.zeros(n * self.L[3])
+        self._chk(lib.ov_timeslice_norm2(self._h, n, _dev(x, (self.V, 4, 3), "x"),
+                                         out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out.reshape(n, self.L[3])
+
+    def pion_correlator(self, props):
+        """Connected pseudoscalar correlator of one flavour, G(t) = sum over the 12 point-source
+        propagators (props: (12, V, 4, 3)) and the sink spin-colour of |S|^2 (gamma5-hermiticity)."""
+        return self.timeslice_norm2(props).sum(axis=0)
 
     def hw_eigensolve(self, field, l, k=None, cheb_order=60, cutoff=0.0, max_iter=20, tol=1e-10, prec="fp64",
                       x0=None, seed=0, install=True, want_vectors=True, raise_on_noconv=True):
