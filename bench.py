@@ -93,7 +93,9 @@ def measured_traffic(prec, nrhs, tuned):
         return None
     if rec.get("source_hash") != kernel_source_hash() or rec.get("prec") != prec or rec.get("nrhs") != nrhs:
         return None
-    if rec.get("tuning") != tuned:
+    rt = dict(rec.get("tuning") or {})
+    rt.setdefault("cols", 1)
+    if rt != tuned:
         return None
     return rec.get("hbm_bytes_per_launch")
 

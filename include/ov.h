@@ -202,7 +202,7 @@ int ov_deflated_cg(ov_ctx *ctx, int nrhs, const int *field_of_rhs, const double 
  * sigma_i)^{-1} b / (1 - m_i^2/4), x_i = D(m_i)^dag y_i, which solves
  * D(m_i) x_i = b because D is normal.  With opts->adaptive the degree of the
  * polynomial for an iteration is the smallest whose error bound (twice the
- * law of eq. (2)) stays below 0.1 tol ||b|| / ||r|| (a less accurate operator
+ * law of eq. (2)) stays below 0.01 tol ||b|| / ||r|| (a less accurate operator
  * is enough while the residual is large), at least min_order; the context's
  * polynomial is restored afterwards.  The shifted solve runs in
  * opts->inner_prec (FP64, or FP32 down to max(tol, 1e-5)) and stops early if
@@ -375,17 +375,20 @@ int ov_set_occupancy(ov_ctx *ctx, int prec, int blocks_per_cu);
 /* Launch shape of precision prec for kind 0 (plain H_w / D_w launches) or
  * kind 1 (launches with the fused Clenshaw epilogue), which ov_autotune tunes
  * separately; the three setters above set both kinds.  cfg is
- * {rhs_per_thread, block, site_order, blocks_per_cu, stream_hint, rhs_split},
- * the first four with the meaning and range given above.  stream_hint 1
+ * {rhs_per_thread, block, site_order, blocks_per_cu, stream_hint, rhs_split,
+ * cols}, the first four with the meaning and range given above.  stream_hint 1
  * marks the operands a launch touches once (epilogue inputs, output)
  * non-temporal so that they do not displace stencil neighbours from L2.
  * rhs_split Q in {1, 2, 4, 8} (Q > 1 only with rhs_per_thread <= 2 and
  * site orders 0, 1; Q = 8 not for BF16 storage) splits each wavefront into Q
  * parts that cover the same 64/Q sites for Q groups of right-hand sides, so
- * each link is fetched once per Q * rhs_per_thread RHS.  Set: OV_EINVAL on a value out of range (nothing
+ * each link is fetched once per Q * rhs_per_thread RHS.  cols (a divisor of
+ * Ly; site order 1 only) walks each XCD's z-slab as cols y-columns one after
+ * the other, which shortens the distance between a site and its t
+ * neighbours in the walk.  Set: OV_EINVAL on a value out of range (nothing
  * changed). */
-int ov_get_launch_config(ov_ctx *ctx, int prec, int kind, int cfg[6]);
-int ov_set_launch_config(ov_ctx *ctx, int prec, int kind, const int cfg[6]);
+int ov_get_launch_config(ov_ctx *ctx, int prec, int kind, int cfg[7]);
+int ov_set_launch_config(ov_ctx *ctx, int prec, int kind, const int cfg[7]);
 int ov_autotune(ov_ctx *ctx, int prec, int nrhs, const char *cache_path);
 
 /*

@@ -92,7 +92,7 @@ struct ov_ctx {
 
     // dslash launch shape per precision and kind (0: plain, 1: fused Clenshaw epilogue)
     struct Launch {
-        int nr = 2, block = 128, order = 0, cap = 0, stream_hint = 0, split = 1;
+        int nr = 2, block = 128, order = 0, cap = 0, stream_hint = 0, split = 1, cols = 1;
     };
     Launch tune[3][2];
 
@@ -415,6 +415,7 @@ int dslash_launch(ov_ctx *c, const Batch &b, const int *fgroup, const S *x, S *y
     d.order = tu.order;
     d.blocks_per_cu = tu.cap;
     d.stream_hint = tu.stream_hint;
+    d.cols = tu.cols;
     if (d.order == 2) {   // t-chunks: enough workgroups to fill the GPU, chunks of at least 4
         const int W = tu.block == 512 ? 8 : 4;   // right-hand sides per workgroup
         const long per_chunk = (long)c->g.Lz * ((c->g.Lxy + 63) / 64) * ((b.n + W - 1) / W);
@@ -1187,6 +1188,7 @@ int ov_get_launch_config(ov_ctx *c, int prec, int kind, int *cfg)
     cfg[3] = tu.cap;
     cfg[4] = tu.stream_hint;
     cfg[5] = tu.split;
+    cfg[6] = tu.cols;
     return OV_OK;
 }
 
@@ -1196,7 +1198,7 @@ int ov_set_launch_config(ov_ctx *c, int prec, int kind, const int *cfg)
     CHK(check_prec(c, prec));
     if (kind != 0 && kind != 1) return fail(c, OV_EINVAL, "kind must be 0 (plain) or 1 (fused epilogue)");
     if (!cfg) return fail(c, OV_EINVAL, "cfg is NULL");
-    const int nr = cfg[0], bl = cfg[1], od = cfg[2], cp = cfg[3], sh = cfg[4], sp = cfg[5];
+    const int nr = cfg[0], bl = cfg[1], od = cfg[2], cp = cfg[3], sh = cfg[4], sp = cfg[5], cl = cfg[6];
     if (nr != 1 && nr != 2 && nr != 4 && nr != 8) return fail(c, OV_EINVAL, "rhs_per_thread must be 1, 2, 4 or 8");
     if (bl != 64 && bl != 128 && bl != 192 && bl != 256 && bl != 512)
         return fail(c, OV_EINVAL, "block must be 64, 128, 192, 256 or 512");
@@ -1206,6 +1208,7 @@ int ov_set_launch_config(ov_ctx *c, int prec, int kind, const int *cfg)
     if (sp != 1 && sp != 2 && sp != 4 && sp != 8) return fail(c, OV_EINVAL, "rhs_split must be 1, 2, 4 or 8");
     if (sp == 8 && prec == OV_BF16) return fail(c, OV_EINVAL, "rhs_split 8 is for FP64 and FP32 storage");
     if (sp > 1 && nr > 2) return fail(c, OV_EINVAL, "rhs_split > 1 needs rhs_per_thread <= 2");
+    if (cl < 1 || cl > 64 || c->g.Ly % cl != 0) return fail(c, OV_EINVAL, "cols must divide Ly (%d)", c->g.Ly);
     invalidate_graphs(c);
     auto &tu = c->tune[prec][kind];
     tu.nr = nr;
@@ -1214,6 +1217,7 @@ int ov_set_launch_config(ov_ctx *c, int prec, int kind, const int *cfg)
     tu.cap = cp;
     tu.stream_hint = sh;
     tu.split = sp;
+    tu.cols = cl;
     return OV_OK;
 }
 
@@ -1785,7 +1789,7 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e9));
         const int nrs[4] = {1, 2, 4, 8}, blks[4] = {64, 128, 256, 512};
-        const int caps[3] = {0, 2, 4}, splits[4] = {1, 2, 4, 8};
+        const int caps[3] = {0, 2, 4}, splits[4] = {1, 2, 4, 8}, colss[3] = {1, 2, 4};
         const int reps = 3;
         const bool was = c->prof_on;
         c->prof_on = false;
@@ -1804,9 +1808,11 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
             float best = 1e30f;
             for (int sh = 0; sh < 2 && rc == OV_OK; ++sh)
             for (int od = 0; od < 4 && rc == OV_OK; ++od)
+            for (int cl : colss)
             for (int cp : caps)
             for (int sp : splits)
             for (int nr : nrs) {
+                if (cl > 1 && (od != 1 || c->g.Ly % cl != 0)) continue;
                 if (sp > 1 && (nr > 2 || od == 2)) continue;
                 if (sp > 1 && (sp / 2) * nr >= nrhs) continue;
                 if (sp == 8 && prec == OV_BF16) continue;
@@ -1825,6 +1831,7 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
                     tu.cap = cp;
                     tu.stream_hint = sh;
                     tu.split = sp;
+                    tu.cols = cl;
                     if (rc == OV_OK) rc = launch();
                     if (rc == OV_OK && hipEventRecord(e0, c->stream) != hipSuccess) rc = OV_EHIP;
                     for (int rep = 0; rep < reps && rc == OV_OK; ++rep) rc = launch();
@@ -1855,10 +1862,10 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
                     std::fprintf(fp,
                                  "{\"arch\": \"gfx950\", \"L\": [%d, %d, %d, %d], \"prec\": %d, \"nrhs\": %d, "
                                  "\"kind\": \"%s\", \"rhs_per_thread\": %d, \"block\": %d, \"site_order\": %d, "
-                                 "\"blocks_per_cu\": %d, \"stream_hint\": %d, \"rhs_split\": %d, "
+                                 "\"blocks_per_cu\": %d, \"stream_hint\": %d, \"rhs_split\": %d, \"cols\": %d, "
                                  "\"ms_per_launch\": %.6f}\n",
                                  c->L[0], c->L[1], c->L[2], c->L[3], prec, nrhs, kind ? "clenshaw" : "dslash",
-                                 tu.nr, tu.block, tu.order, tu.cap, tu.stream_hint, tu.split, best_ms[kind]);
+                                 tu.nr, tu.block, tu.order, tu.cap, tu.stream_hint, tu.split, tu.cols, best_ms[kind]);
                 }
                 std::fclose(fp);
             }
@@ -2340,7 +2347,7 @@ int api_mscg(ov_ctx *c, int nrhs, const std::vector<int> &grp, int nm, const dou
         // 1. order of this application (relaxation: the operator may be less accurate
         //    as the residual falls)
         if (o.adaptive) {
-            const int ord = adaptive_order(0.1 * inner_tol / std::max(rho, 1e-300), c->eps, o.min_order, n_full);
+            const int ord = adaptive_order(0.01 * inner_tol / std::max(rho, 1e-300), c->eps, o.min_order, n_full);
             if (ord != cur_order) {
                 cur_order = ord;
                 c->npoly = ord;

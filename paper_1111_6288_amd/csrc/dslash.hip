@@ -285,7 +285,7 @@ __device__ __forceinline__ int xcd_block(int b, int nblk)
 // per site, against 2/(Lz/8) for order 1).  orders 1 and 3 need Lz % 8 == 0
 // (Lt % 8 == 0) and V % 64 == 0 (no padding); the launcher checks.
 template <int Q>
-__device__ __forceinline__ int dslash_site(const Geo &g, int order, int xcd_remap)
+__device__ __forceinline__ int dslash_site(const Geo &g, int order, int xcd_remap, int cols)
 {
     constexpr int SL = 64 / Q;   // sites per wave
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -301,11 +301,17 @@ __device__ __forceinline__ int dslash_site(const Geo &g, int order, int xcd_rema
         return o + g.Lxy * (z + g.Lz * (xcd * nt + tl));
     }
     if (order == 1) {
+        // with cols > 1 the slab is walked one y-column (Ly/cols rows) at a time,
+        // which shortens the distance between a site and its t neighbours
         const int xcd = blockIdx.x & 7;
         const int u = (blockIdx.x >> 3) * spb + tb;
         const int nz = g.Lz >> 3;
-        const int q = u / g.Lxy, o = u - q * g.Lxy;
-        if (q >= nz * g.Lt) return g.Vp;   // beyond the slab: no work
+        const int P = g.Lxy / cols;                 // sites of one column in one (z, t) plane
+        const int per_col = P * nz * g.Lt;
+        const int col = u / per_col;
+        if (col >= cols) return g.Vp;               // beyond the slab: no work
+        const int rem = u - col * per_col;
+        const int q = rem / P, o = rem - q * P + col * P;
         const int zl = q % nz, t = q / nz;
         return o + g.Lxy * (xcd * nz + zl + g.Lz * t);
     }
@@ -321,7 +327,7 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
 {
     using R = typename StoreT<S>::real;
     const Geo &g = a.g;
-    const int site = dslash_site<Q>(g, a.order, a.xcd_remap);
+    const int site = dslash_site<Q>(g, a.order, a.xcd_remap, a.cols);
     if (site >= g.Vp) return;
     const int sub = (int)(threadIdx.x & 63) / (64 / Q);
     const int j0 = (blockIdx.y * Q + sub) * NR;
@@ -569,6 +575,7 @@ static hipError_t launch_nr(const DsArgs<S> &a, bool hw, bool epi, int block, hi
     DsArgs<S> b = a;
     b.xcd_remap = 0;
     if (b.order == 1 && (a.g.Lz % 8 != 0 || a.g.V % 64 != 0)) b.order = 0;
+    if (b.cols < 1 || a.g.Ly % b.cols != 0) b.cols = 1;
     if (b.order == 3 && (a.g.Lt % 8 != 0 || a.g.V % 64 != 0)) b.order = 0;
     if (b.order == 2) b.order = 0;   // t-marching shapes that cannot march use order 0
     if (b.order == 1 || b.order == 3) {

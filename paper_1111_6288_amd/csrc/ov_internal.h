@@ -30,6 +30,7 @@ struct DsArgs {
     int blocks_per_cu;       // occupancy cap (0: none), enforced through reserved LDS
     int xcd_remap;           // set by the launcher
     int stream_hint;         // 1: epilogue inputs and the output bypass cache retention (non-temporal)
+    int cols;                // order 1: the slab is walked as `cols` y-columns, one after the other
 };
 
 template <class S>

@@ -405,11 +405,11 @@ class Context:
         return self._chk(lib.ov_set_occupancy(self._h, PREC[prec], int(blocks_per_cu)))
 
     _KIND = {"dslash": 0, "clenshaw": 1}
-    _CFG = ("rhs_per_thread", "block", "site_order", "blocks_per_cu", "stream_hint", "rhs_split")
+    _CFG = ("rhs_per_thread", "block", "site_order", "blocks_per_cu", "stream_hint", "rhs_split", "cols")
 
     def get_launch_config(self, prec, kind="dslash"):
         """Launch shape of the plain ("dslash") or fused-epilogue ("clenshaw") launches of prec."""
-        cfg = (C.c_int * 6)()
+        cfg = (C.c_int * 7)()
         self._chk(lib.ov_get_launch_config(self._h, PREC[prec], self._KIND[kind], cfg))
         return dict(zip(self._CFG, list(cfg)))
 
@@ -420,7 +420,7 @@ class Context:
             if k not in cur:
                 raise KeyError(k)
             cur[k] = int(v)
-        arr = (C.c_int * 6)(*[cur[k] for k in self._CFG])
+        arr = (C.c_int * 7)(*[cur[k] for k in self._CFG])
         return self._chk(lib.ov_set_launch_config(self._h, PREC[prec], self._KIND[kind], arr))
 
     def get_tuning(self, prec):
@@ -448,6 +448,8 @@ class Context:
             if (e.get("arch") != "gfx950" or tuple(e.get("L", ())) != self.L or e.get("prec") != PREC[prec]
                     or e.get("nrhs") != int(nrhs) or e.get("kind") not in self._KIND):
                 continue
-            self.set_launch_config(prec, e["kind"], **{k: e[k] for k in self._CFG})
+            defaults = {"stream_hint": 0, "rhs_split": 1, "cols": 1}
+            self.set_launch_config(prec, e["kind"], **{k: e.get(k, defaults.get(k)) for k in self._CFG
+                                                       if k in e or k in defaults})
             applied.append(e["kind"])
         return applied

@@ -164,9 +164,11 @@ def test_dslash_rhs_split(L, bc, split, nr, block):
             with pytest.raises(_ov().OvError):
                 ctx.set_launch_config(prec, "dslash", rhs_split=8, rhs_per_thread=nr)
             continue
-        for order in (0, 1, 3):
+        for order, cols in ((0, 1), (1, 1), (3, 1), (1, 2), (1, L[1])):
+            if L[1] % cols:
+                continue
             ctx.set_launch_config(prec, "dslash", rhs_per_thread=nr, block=block, site_order=order,
-                                  blocks_per_cu=0, stream_hint=order % 2, rhs_split=split)
+                                  blocks_per_cu=0, stream_hint=order % 2, rhs_split=split, cols=cols)
             for op, opc in (("HW", 1), ("DW", 0)):
                 y = _np(ctx.dslash(_t(x), f, op=op, prec=prec))
                 for j in range(nrhs):
@@ -197,7 +199,7 @@ def test_stream_hint_and_per_kind_shapes(order, block, nr, split):
                               blocks_per_cu=2, stream_hint=1, rhs_split=4 if order != 1 else 1)
         got = ctx.get_launch_config(prec, "dslash")
         assert got == dict(rhs_per_thread=nr, block=block, site_order=order, blocks_per_cu=0, stream_hint=1,
-                           rhs_split=split)
+                           rhs_split=split, cols=1)
         y = _np(ctx.dslash(_t(x), f, prec=prec))
         for j in (0, 1, 8):
             lat = api.Lattice(L, bc, MW, U, (2 / 3 * 1e-3, -1 / 3 * 0.2)[f[j]])
@@ -217,7 +219,8 @@ def test_launch_config_rejects_bad_values():
     ov = _ov()
     good = ctx.get_launch_config("fp32", "clenshaw")
     for bad in (dict(rhs_per_thread=3), dict(block=96), dict(site_order=4), dict(blocks_per_cu=-1),
-                dict(stream_hint=2), dict(rhs_split=3), dict(rhs_per_thread=4, rhs_split=2)):
+                dict(stream_hint=2), dict(rhs_split=3), dict(rhs_per_thread=4, rhs_split=2), dict(cols=3),
+                dict(cols=0)):
         with pytest.raises(ov.OvError):
             ctx.set_launch_config("fp32", "clenshaw", **bad)
         assert ctx.get_launch_config("fp32", "clenshaw") == good
