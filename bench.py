@@ -83,6 +83,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def synth_volume():
+    return L[0] * L[1] * L[2] * L[3]
+
+
 def measured_traffic(prec, nrhs, tuned):
     """HBM bytes per launch of the Clenshaw kernel from committed rocprofv3 PMC runs, if they were
     taken on the current kernel source in the same launch configuration."""
@@ -332,6 +336,7 @@ def main():
         ctx.autotune("fp32", nrhs)
     if not args.autotune:
         ctx.load_tuning(TUNING_FILE, "fp64", nrhs)
+        ctx.load_tuning(TUNING_FILE, "bf16", nrhs)
     tuned = {k: ctx.get_launch_config("fp32", k) for k in ("dslash", "clenshaw")}
     print(f"[bench] setup {t_setup:.1f}s, fp32 tuning {tuned}", file=sys.stderr, flush=True)
 
@@ -345,6 +350,7 @@ def main():
     ctx.dov_apply(x, fields, masses, dagger=False, prec="fp32", out=y32)
     fp64 = None
     err = None
+    extra = {}
     if not args.no_fp64:
         y64 = torch.empty_like(x)
         dt64, _ = timed_applies(torch, ctx, x, y64, fields, masses, "fp64", args.fp64_steps, 1, False)
@@ -352,9 +358,22 @@ def main():
         ctx.dov_apply(x, fields, masses, dagger=False, prec="fp64", out=y64)
         d = (y32 - y64).reshape(nrhs, -1).norm(dim=1) / y64.reshape(nrhs, -1).norm(dim=1)
         err = float(d.max())
-        del y64
         print(f"[bench] fp64: {fp64:.2f} applies/s; mixed vs fp64 max rel err {err:.2e}", file=sys.stderr,
               flush=True)
+        # BF16 storage (FP32 arithmetic) on the same 108 RHS, and FP64 on a single RHS
+        y16 = torch.empty_like(x)
+        dt16, _ = timed_applies(torch, ctx, x, y16, fields, masses, "bf16", 1, 1, False)
+        extra["bf16_applies_per_s"] = round(nrhs / dt16, 3)
+        ctx.dov_apply(x, fields, masses, dagger=False, prec="bf16", out=y16)
+        d16 = (y16 - y64).reshape(nrhs, -1).norm(dim=1) / y64.reshape(nrhs, -1).norm(dim=1)
+        extra["bf16_vs_fp64_max_rel_err"] = float(d16.max())
+        del y16, y64
+        x1 = x[:1].clone()
+        y1 = torch.empty_like(x1)
+        dt1, _ = timed_applies(torch, ctx, x1, y1, fields[:1], masses[:1], "fp64", 3, 1, False)
+        extra["fp64_single_rhs_applies_per_s"] = round(3 / dt1, 3)
+        print(f"[bench] bf16: {extra['bf16_applies_per_s']} applies/s, fp64 single RHS: "
+              f"{extra['fp64_single_rhs_applies_per_s']} applies/s", file=sys.stderr, flush=True)
 
     n_launch, ms, by = stats["clenshaw"]
     avg_ms = ms / max(n_launch, 1)
@@ -372,6 +391,14 @@ def main():
                 "algorithmic_bytes_per_launch": bytes_per_launch}
     kernels = {k: {"launches": v[0], "ms": round(v[1], 2), "GBps": round(v[2] / max(v[1], 1e-9) / 1e6, 1)}
                for k, v in stats.items()}
+    # V^dag X on the matrix cores: 8 l n K flops per launch (one field group of n RHS, K = 12 Vp)
+    n_pd, ms_pd, _ = stats["proj_dot"]
+    n_grp = nrhs // len(ETAS)
+    Vp = (synth_volume() + 63) // 64 * 64
+    flops = n_pd * 8.0 * args.lsmall * n_grp * 12 * Vp
+    tf = flops / max(ms_pd * 1e-3, 1e-12) / 1e12 if n_pd else None
+    projection = {"kernel": "k_proj_dot_mfma<float2> (V^dag X, FP64 MFMA)", "tflops": None if tf is None else round(tf, 2),
+                  "peak_tflops": 78.6, "frac": None if tf is None else round(tf / 78.6, 4)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -393,6 +420,8 @@ def main():
         "mixed_vs_fp64_max_rel_err": err,
         "roofline": roofline,
         "kernels": kernels,
+        "projection": projection,
+        **extra,
         "cpu_baseline": cpu,
     }
     ctx.close()
