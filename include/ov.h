@@ -314,6 +314,22 @@ int ov_dov_eigensolve(ov_ctx *ctx, int field, int chirality, const ov_eig_opts *
 int ov_timeslice_norm2(ov_ctx *ctx, int nrhs, const void *x_dev, double *out);
 
 /*
+ * Derivative of a correlator with respect to the background field (Sec. 4:
+ * the pion's energy shift comes from G_E(t) / G_0(t); the polarizability is a
+ * derivative in the field strength).  For field group `field` and mass m:
+ *   S_j = D(m)^{-1} b_j (deflated CG with *opts),
+ *   C[t] = sum_j sum over time slice t of |S_j|^2   (host [Lt], may be NULL),
+ *   F = sum_t w[t] C[t],  *dF = dF/deta with the charge q held fixed,
+ * through the solve: mu_j = D(m)^{-1} (gamma5 W S_j) (W = w by time slice),
+ * dF/deta = -2 (1 - m/2) sum_j d/deta Re<mu_j, s(eta) S_j>, the last factor
+ * from the sign adjoint (as ov_sign_backward: small space and polynomial held
+ * fixed).  2 nsrc solves and nsrc sign adjoints.  b_dev [nsrc][V][4][3]
+ * complex128.  Allocates its temporaries.  Synchronises.
+ */
+int ov_correlator_deta(ov_ctx *ctx, int field, double mass, int nsrc, const void *b_dev, const double *w,
+                       double *C, double *dF, const ov_cg_opts *opts);
+
+/*
  * Host utility (no context, no GPU): eigen-decomposition of a Hermitian
  * n x n matrix by cyclic Jacobi rotations, as the eigensolver's
  * Rayleigh-Ritz step uses it.  A: column-major complex (interleaved re, im),

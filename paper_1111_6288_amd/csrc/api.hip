@@ -2778,3 +2778,73 @@ int ov_timeslice_norm2(ov_ctx *c, int nrhs, const void *x_dev, double *out)
 }
 
 }  // extern "C"
+
+extern "C" {
+
+// F = sum_t w_t C(t), C(t) = sum_j sum_{x in t} |S_j(x)|^2, S_j = D(m)^{-1} b_j; dF/deta through
+// the solve: with mu_j = D^{-1} (gamma5 W S_j), dF/deta = -2 (1 - m/2) sum_j d/deta Re<mu_j, s S_j>
+// (the sign adjoint of ov_sign_backward, small space and polynomial held fixed).
+int ov_correlator_deta(ov_ctx *c, int field, double mass, int nsrc, const void *b_dev, const double *w,
+                       double *C, double *dF, const ov_cg_opts *opts)
+{
+    CHK(check_ctx(c));
+    if (field < 0 || field >= c->nfield) return fail(c, OV_EINVAL, "field %d outside [0, %d)", field, c->nfield);
+    if (nsrc < 1 || nsrc > 4096) return fail(c, OV_EINVAL, "nsrc outside [1, 4096]");
+    if (!b_dev || !w || !opts) return fail(c, OV_EINVAL, "null argument");
+    if (!c->have_gauge || !c->have_sign) return fail(c, OV_ESTATE, "upload the gauge field and set the sign first");
+    if (!(mass >= 0 && mass < 2)) return fail(c, OV_EINVAL, "mass outside [0, 2)");
+    const int Lt = c->g.Lt;
+    const size_t fb = 16ul * 12 * c->g.V * nsrc;
+    double2 *S = nullptr, *R = nullptr, *M = nullptr;
+    double *wd = nullptr;
+    std::vector<double> ts((size_t)nsrc * Lt);
+    auto cleanup = [&]() {
+        dev_free(c, S, fb);
+        dev_free(c, R, fb);
+        dev_free(c, M, fb);
+        dev_free(c, wd, 8ul * Lt);
+    };
+    int rc = dev_alloc(c, (void **)&S, fb);
+    if (rc == OV_OK) rc = dev_alloc(c, (void **)&R, fb);
+    if (rc == OV_OK) rc = dev_alloc(c, (void **)&M, fb);
+    if (rc == OV_OK) rc = dev_alloc(c, (void **)&wd, 8ul * Lt);
+    if (rc != OV_OK) {
+        cleanup();
+        return rc;
+    }
+    std::vector<int> grp(nsrc, field);
+    std::vector<double> mv(nsrc, mass);
+    std::vector<ov_cg_rhs_report> rep(nsrc);
+    auto solve = [&](const double2 *b, double2 *x) -> int {
+        HIPCHK(hipMemsetAsync(x, 0, fb, c->stream));
+        if (opts->inner_prec == OV_FP64) return api_cg<double2>(c, nsrc, grp, mv.data(), b, x, *opts, rep.data());
+        if (opts->inner_prec == OV_BF16) return api_cg<uint32_t>(c, nsrc, grp, mv.data(), b, x, *opts, rep.data());
+        return api_cg<float2>(c, nsrc, grp, mv.data(), b, x, *opts, rep.data());
+    };
+    rc = solve((const double2 *)b_dev, S);
+    if (rc == OV_OK) rc = ov_timeslice_norm2(c, nsrc, S, ts.data());
+    if (rc == OV_OK && h2d(c, wd, w, 8ul * Lt) != hipSuccess) rc = fail(c, OV_EHIP, "weight upload failed");
+    if (rc == OV_OK && launch_weight_g5(S, wd, c->g.V, c->g.Lxyz, nsrc, R, c->stream) != hipSuccess)
+        rc = fail(c, OV_EHIP, "weighting kernel failed");
+    if (rc == OV_OK) rc = solve(R, M);
+    double acc = 0.0;
+    for (int j = 0; j < nsrc && rc == OV_OK; ++j) {
+        double ge = 0.0;
+        rc = api_backward(c, field, S + (size_t)j * 12 * c->g.V, M + (size_t)j * 12 * c->g.V, nullptr, &ge, nullptr,
+                          std::min(32, c->npoly));
+        acc += ge;
+    }
+    if (rc == OV_OK) {
+        if (C)
+            for (int t = 0; t < Lt; ++t) {
+                double s = 0;
+                for (int j = 0; j < nsrc; ++j) s += ts[(size_t)j * Lt + t];
+                C[t] = s;
+            }
+        if (dF) *dF = -2.0 * (1.0 - 0.5 * mass) * acc;
+    }
+    cleanup();
+    return rc;
+}
+
+}  // extern "C"

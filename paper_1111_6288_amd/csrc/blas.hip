@@ -100,6 +100,28 @@ __global__ void k_slice_finish(const double *__restrict__ part, int nb, int m, d
     out[e] = s;
 }
 
+// out_j(x) = w[t(x)] gamma5 in_j(x), canonical complex128 [n][V][12] (spin = k / 3).
+__global__ __launch_bounds__(256) void k_weight_g5(const double2 *__restrict__ in, const double *__restrict__ w,
+                                                   long V, int Lxyz, int n, double2 *__restrict__ out)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)n * V * 12) return;
+    const long site = (e / 12) % V;
+    const int k = (int)(e % 12);
+    const double s = w[site / Lxyz] * (k < 6 ? 1.0 : -1.0);
+    const double2 v = in[e];
+    out[e] = make_double2(s * v.x, s * v.y);
+}
+
+hipError_t launch_weight_g5(const double2 *in, const double *w, long V, int Lxyz, int n, double2 *out,
+                            hipStream_t st)
+{
+    const long m = (long)n * V * 12;
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_weight_g5, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, in, w, V, Lxyz, n, out);
+    return hipGetLastError();
+}
+
 // Count of non-finite doubles in a buffer (result accumulated atomically).
 __global__ void k_count_nonfinite(const double *__restrict__ p, long n, int *count)
 {

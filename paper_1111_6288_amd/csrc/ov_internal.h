@@ -100,6 +100,8 @@ struct ForceArgs {
 };
 hipError_t launch_force(const ForceArgs &a, hipStream_t st);
 int slice_norm2_blocks(int Lxyz);
+hipError_t launch_weight_g5(const double2 *in, const double *w, long V, int Lxyz, int n, double2 *out,
+                            hipStream_t st);
 hipError_t launch_slice_norm2(const double2 *x, int n, long V, int Lxyz, int Lt, double *part, double *out,
                               hipStream_t st);
 hipError_t launch_force_finish(const double2 *G, const double2 *U, const cx<double> *phase_row, double q,

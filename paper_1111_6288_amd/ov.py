@@ -93,6 +93,7 @@ def _load():
         "ov_multishift_cg": ([vp, i, cp(i), i, cp(d), vp, vp, cp(MscgOpts), cp(MscgReport), cp(d)], i),
         "ov_dov_eigensolve": ([vp, i, i, cp(EigOpts), vp, vp, cp(d), cp(d), i, cp(EigReport)], i),
         "ov_timeslice_norm2": ([vp, i, vp, cp(d)], i),
+        "ov_correlator_deta": ([vp, i, d, i, vp, cp(d), cp(d), cp(d), cp(CgOpts)], i),
         "ov_prof_enable": ([vp, i], i),
         "ov_prof_query": ([vp, C.c_char_p, cp(C.c_long), cp(d), cp(d)], i),
         "ov_set_tuning": ([vp, i, i, i], i),
@@ -120,7 +121,7 @@ EXPORTED = ("ov_create", "ov_destroy", "ov_set_stream", "ov_last_error", "ov_upl
             "ov_set_tuning", "ov_get_tuning", "ov_autotune", "ov_memory_used", "ov_set_graphs",
             "ov_set_site_order", "ov_set_occupancy", "ov_get_launch_config",
             "ov_set_launch_config", "ov_hw_eigensolve", "ov_dense_heev", "ov_multishift_cg",
-            "ov_dov_eigensolve", "ov_timeslice_norm2")
+            "ov_dov_eigensolve", "ov_timeslice_norm2", "ov_correlator_deta")
 
 
 def _ints(v):
@@ -354,6 +355,21 @@ class Context:
         self._chk(lib.ov_timeslice_norm2(self._h, n, _dev(x, (self.V, 4, 3), "x"),
                                          out.ctypes.data_as(C.POINTER(C.c_double))))
         return out.reshape(n, self.L[3])
+
+    def correlator_deta(self, b, field, mass, weights, tol=1e-10, inner_prec="fp32"):
+        """(C(t), dF/deta) with F = sum_t weights[t] C(t) for the propagators of sources b
+        (ov_correlator_deta)."""
+        import numpy as np
+        b = b.reshape(-1, self.V, 4, 3).contiguous()
+        n = int(b.shape[0])
+        Ct = np.zeros(self.L[3])
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        dF = C.c_double(0.0)
+        opts = CgOpts(float(tol), 10000, PREC[inner_prec], 1e-5, 50, 1)
+        self._chk(lib.ov_correlator_deta(self._h, int(field), float(mass), n, _dev(b, (self.V, 4, 3), "b"),
+                                         w.ctypes.data_as(C.POINTER(C.c_double)),
+                                         Ct.ctypes.data_as(C.POINTER(C.c_double)), C.byref(dF), C.byref(opts)))
+        return Ct, dF.value
 
     def pion_correlator(self, props):
         """Connected pseudoscalar correlator of one flavour, G(t) = sum over the 12 point-source

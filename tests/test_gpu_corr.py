@@ -70,3 +70,45 @@ def test_ratio_R_end_to_end():
     assert np.abs(R_gpu - R_ref).max() < 1e-8 * np.abs(R_ref).max()
     # the field changes the correlator (R is not identically 1)
     assert np.abs(R_ref - 1).max() > 1e-6
+
+
+def test_correlator_derivative_against_finite_differences():
+    """dF/deta for F = sum_t w_t C(t) through the solve and the sign adjoint, against central
+    differences of the dense construction with the small space and polynomial held fixed
+    (the same reading as the adjoint); C(t) itself against the dense solve."""
+    from paper_1111_6288_amd import ov
+    L, bc = (4, 4, 4, 4), (2, 0, 0, 2)
+    U = synth.su3_links(L, 0.3, 31)
+    q, eta0, m = 2 / 3, 0.3, 0.1
+    n, l = 140, 16
+    H0 = dense.dense_hw(L, bc, MW, U, q * eta0)
+    Vs, lam = dense.small_space(H0, l)
+    w = np.sort(np.abs(np.linalg.eigvalsh(H0)))
+    eps = (w[l] / NORM) ** 2 * 0.9
+    c = api.cheb_coeffs(n, eps)
+    Vm = Vs.reshape(l, -1).T
+    Pi = np.eye(Vm.shape[0]) - Vm @ Vm.conj().T
+    Sg = Vm @ np.diag(np.where(np.asarray(lam) >= 0, 1.0, -1.0)) @ Vm.conj().T
+    b = synth.point_sources(L, (2, 0, 0, 1))[[0, 5, 7, 10]]
+    wts = np.array([0.0, 1.0, 0.6, 0.3])
+
+    def F_dense(eta):
+        H = dense.dense_hw(L, bc, MW, U, q * eta)
+        Qp, _, _, _ = dense.spectral_sign(H, NORM, n, eps, c, 0)
+        D = dense.dense_dm(Sg + Pi @ Qp @ Pi, m)
+        props = np.stack([np.linalg.solve(D, bj.ravel()).reshape(bj.shape) for bj in b])
+        Ct = corr.pion_correlator(props, L)
+        return Ct, float(wts @ Ct)
+
+    C0, _ = F_dense(eta0)
+    h = 1e-4
+    dF_fd = (F_dense(eta0 + h)[1] - F_dense(eta0 - h)[1]) / (2 * h)
+    ctx = ov.Context(L, bc, MW)
+    ctx.upload_gauge(_t(U))
+    ctx.set_fields([q], [eta0])
+    ctx.set_sign_params(n, eps, NORM)
+    ctx.upload_eigvecs(0, _t(Vs), lam)
+    Cg, dF = ctx.correlator_deta(_t(b), 0, m, wts, tol=1e-11)
+    assert np.abs(Cg - C0).max() < 1e-8 * np.abs(C0).max()
+    assert abs(dF - dF_fd) < 1e-5 * abs(dF_fd), (dF, dF_fd)
+    assert abs(dF_fd) > 1e-6
