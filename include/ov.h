@@ -93,6 +93,26 @@ const char *ov_last_error(const ov_ctx *ctx);
 int ov_upload_gauge(ov_ctx *ctx, const void *U_dev);
 
 /*
+ * Link storage read by the dslash kernels.  Every SU(3) matrix satisfies
+ * u_2a = conj(u_0b u_1c - u_0c u_1b) for (a, b, c) cyclic (its third row is
+ * the conjugated cross product of the first two), so the kernels can read
+ * two rows and rebuild the third, two thirds of the link bytes.  The upload
+ * measures, in FP64, the largest deviation of the uploaded links from this
+ * identity; the two-row kernels are used while reconstruction is enabled
+ * (the default) and that deviation is at most 1e-14; otherwise all nine
+ * entries are read.  The result of either path is the operator of the
+ * uploaded links to within that bound.
+ *
+ * ov_set_link_reconstruct: enable (1, default) or disable (0) the two-row
+ * path for this context; OV_EINVAL for other values.
+ * ov_get_link_format: *reconstruct = 1 if the two-row kernels are in use;
+ * *row3_dev = the measured deviation (-1 before the first upload).  Either
+ * pointer may be NULL.
+ */
+int ov_set_link_reconstruct(ov_ctx *ctx, int enable);
+int ov_get_link_format(ov_ctx *ctx, int *reconstruct, double *row3_dev);
+
+/*
  * Define nfield background-field groups: group f multiplies the mu = 0 links
  * by exp(i q[f] eta[f] t) (Sec. 4, eq. (3); the operator depends on q*eta
  * only).  Host arrays of length nfield (1 <= nfield <= 64).  Resets any small

@@ -64,6 +64,9 @@ struct ov_ctx {
     std::string err;
 
     bool have_gauge = false;
+    bool recon_allow = true;         // use two-row links when the uploaded links are SU(3)
+    bool recon = false;              // kernels read two rows and rebuild the third
+    double row3_dev = -1;            // max |u_2 - conj(u_0 x u_1)| of the uploaded links
     double2 *U64 = nullptr;
     float2 *U32 = nullptr;
     uint32_t *U16 = nullptr;
@@ -174,6 +177,19 @@ void invalidate_graphs(ov_ctx *c)
     for (auto &kv : c->graphs)
         if (kv.second.second) (void)hipGraphExecDestroy(kv.second.second);
     c->graphs.clear();
+}
+
+// Two-row links are used only when every uploaded link satisfies the SU(3)
+// row identity to FP64 rounding (entries of an SU(3) matrix are at most 1 in
+// modulus, so the bound is absolute); the captured pipelines hold the kernel
+// choice, so a change of format drops them.
+constexpr double kRow3Tol = 1e-14;
+
+void update_link_format(ov_ctx *c)
+{
+    const bool r = c->recon_allow && c->have_gauge && c->row3_dev >= 0 && c->row3_dev <= kRow3Tol;
+    if (r != c->recon) invalidate_graphs(c);
+    c->recon = r;
 }
 
 // Make sure the arena holds `bytes`; only called before any pointer is handed out.
@@ -416,6 +432,7 @@ int dslash_launch(ov_ctx *c, const Batch &b, const int *fgroup, const S *x, S *y
     d.blocks_per_cu = tu.cap;
     d.stream_hint = tu.stream_hint;
     d.cols = tu.cols;
+    d.recon = c->recon ? 1 : 0;
     if (d.order == 2) {   // t-chunks: enough workgroups to fill the GPU, chunks of at least 4
         const int W = tu.block == 512 ? 8 : 4;   // right-hand sides per workgroup
         const long per_chunk = (long)c->g.Lz * ((c->g.Lxy + 63) / 64) * ((b.n + W - 1) / W);
@@ -935,8 +952,33 @@ int ov_upload_gauge(ov_ctx *c, const void *U_dev)
     HIPCHK(launch_pack_links<double2>((const double2 *)U_dev, c->U64, c->g.V, c->g.Vp, c->stream));
     HIPCHK(launch_pack_links<float2>((const double2 *)U_dev, c->U32, c->g.V, c->g.Vp, c->stream));
     HIPCHK(launch_pack_links<uint32_t>((const double2 *)U_dev, c->U16, c->g.V, c->g.Vp, c->stream));
+    unsigned long long *d_dev = (unsigned long long *)((char *)c->d_count + 8);
+    unsigned long long dev_bits = 0;
+    HIPCHK(hipMemsetAsync(d_dev, 0, sizeof(dev_bits), c->stream));
+    HIPCHK(launch_link_row3_dev((const double2 *)U_dev, 4L * c->g.V, d_dev, c->stream));
+    HIPCHK(hipMemcpyAsync(&dev_bits, d_dev, sizeof(dev_bits), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    std::memcpy(&c->row3_dev, &dev_bits, sizeof(double));
     c->have_gauge = true;
+    update_link_format(c);
+    return OV_OK;
+}
+
+int ov_set_link_reconstruct(ov_ctx *c, int enable)
+{
+    CHK(check_ctx(c));
+    if (enable != 0 && enable != 1) return fail(c, OV_EINVAL, "enable must be 0 or 1");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->recon_allow = enable != 0;
+    update_link_format(c);
+    return OV_OK;
+}
+
+int ov_get_link_format(ov_ctx *c, int *reconstruct, double *row3_dev)
+{
+    CHK(check_ctx(c));
+    if (reconstruct) *reconstruct = c->recon ? 1 : 0;
+    if (row3_dev) *row3_dev = c->row3_dev;
     return OV_OK;
 }
 
@@ -1863,9 +1905,10 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
                                  "{\"arch\": \"gfx950\", \"L\": [%d, %d, %d, %d], \"prec\": %d, \"nrhs\": %d, "
                                  "\"kind\": \"%s\", \"rhs_per_thread\": %d, \"block\": %d, \"site_order\": %d, "
                                  "\"blocks_per_cu\": %d, \"stream_hint\": %d, \"rhs_split\": %d, \"cols\": %d, "
-                                 "\"ms_per_launch\": %.6f}\n",
+                                 "\"two_row_links\": %d, \"ms_per_launch\": %.6f}\n",
                                  c->L[0], c->L[1], c->L[2], c->L[3], prec, nrhs, kind ? "clenshaw" : "dslash",
-                                 tu.nr, tu.block, tu.order, tu.cap, tu.stream_hint, tu.split, tu.cols, best_ms[kind]);
+                                 tu.nr, tu.block, tu.order, tu.cap, tu.stream_hint, tu.split, tu.cols,
+                                 c->recon ? 1 : 0, best_ms[kind]);
                 }
                 std::fclose(fp);
             }

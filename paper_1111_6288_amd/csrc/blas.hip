@@ -131,6 +131,30 @@ __global__ void k_count_nonfinite(const double *__restrict__ p, long n, int *cou
     if (bad) atomicAdd(count, bad);
 }
 
+// How far each link is from the SU(3) identity u_2 = conj(u_0 x u_1) (rows
+// u_0, u_1, u_2, cross product over the colour index), in FP64.  One wave
+// reduces its lanes before the atomic.  Non-negative doubles order like their
+// bit patterns, so an unsigned 64-bit max is a max of the values.
+__global__ __launch_bounds__(256) void k_link_row3_dev(const double2 *__restrict__ U, long nl,
+                                                       unsigned long long *out)
+{
+    double worst = 0;
+    for (long l = blockIdx.x * (long)blockDim.x + threadIdx.x; l < nl; l += (long)gridDim.x * blockDim.x) {
+        const double2 *m = U + 9 * l;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int b = (a + 1) % 3, c = (a + 2) % 3;
+            const double2 p = m[b], q = m[3 + c], r = m[c], s = m[3 + b];
+            const double tr = (p.x * q.x - p.y * q.y) - (r.x * s.x - r.y * s.y);
+            const double ti = (p.x * q.y + p.y * q.x) - (r.x * s.y + r.y * s.x);
+            const double dr = m[6 + a].x - tr, di = m[6 + a].y + ti;
+            worst = fmax(worst, sqrt(dr * dr + di * di));
+        }
+    }
+    for (int w = 32; w >= 1; w >>= 1) worst = fmax(worst, __shfl_xor(worst, w, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(worst));
+}
+
 // ---------------------------------------------------------------- lincomb
 // out_s = sum_j coef_j(s) * G_j in_j,s   (G_j = gamma5 if bit j of g5mask)
 // optionally red[s][blk] = sum |out_s|^2 over this block's elements.
@@ -350,6 +374,15 @@ hipError_t launch_count_nonfinite(const double *p, long n, int *count, hipStream
     if (nb > 4096) nb = 4096;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_count_nonfinite, dim3(nb), dim3(256), 0, st, p, n, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_link_row3_dev(const double2 *U, long nl, unsigned long long *out, hipStream_t st)
+{
+    long nb = (nl + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_link_row3_dev, dim3(nb), dim3(256), 0, st, U, nl, out);
     return hipGetLastError();
 }
 

@@ -129,14 +129,32 @@ __device__ __forceinline__ void stpair_nt(S *__restrict__ f, int Vp, int p, unsi
 }
 
 // Link U_mu(s): components 0..7 as pairs, component 8 on its own plane.
-template <class S, class R>
+// REC: only the first two rows are read (components 0..5, three pairs) and
+// the third is rebuilt as u_2a = conj(u_0b u_1c - u_0c u_1b), (a, b, c)
+// cyclic, the identity that an SU(3) matrix (unitary, det 1) satisfies.  The
+// gauge upload measures how far the stored links are from it and selects
+// these kernels only where it holds to FP64 rounding; they read two thirds of
+// the link bytes.
+template <class S, class R, bool REC>
 __device__ __forceinline__ void load_link(const S *__restrict__ U, int mu, int Vp, unsigned s, cx<R> (&u)[3][3])
 {
     const S *b = U + (size_t)(mu * 9) * (unsigned)Vp;
+    if constexpr (REC) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
-        ldpair<S, R>(b, Vp, p, s, u[(2 * p) / 3][(2 * p) % 3], u[(2 * p + 1) / 3][(2 * p + 1) % 3]);
-    u[2][2] = ldp<S, R>(b + (size_t)8 * (unsigned)Vp, s);
+        for (int p = 0; p < 3; ++p)
+            ldpair<S, R>(b, Vp, p, s, u[(2 * p) / 3][(2 * p) % 3], u[(2 * p + 1) / 3][(2 * p + 1) % 3]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int b1 = (a + 1) % 3, c1 = (a + 2) % 3;
+            const cx<R> t = csub(cmul(u[0][b1], u[1][c1]), cmul(u[0][c1], u[1][b1]));
+            u[2][a] = cmk(t.x, -t.y);
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+            ldpair<S, R>(b, Vp, p, s, u[(2 * p) / 3][(2 * p) % 3], u[(2 * p + 1) / 3][(2 * p + 1) % 3]);
+        u[2][2] = ldp<S, R>(b + (size_t)8 * (unsigned)Vp, s);
+    }
 }
 
 template <class S, class R>
@@ -186,7 +204,7 @@ __device__ __forceinline__ void write_site(const DsArgs<S> &a, size_t off, unsig
 }
 
 // One direction, both hops, for all NR right-hand sides of this thread.
-template <int MU, int NR, class S, class R>
+template <int MU, int NR, class S, class R, bool REC>
 __device__ __forceinline__ void hop_dir(const DsArgs<S> &a, int site, int cmu, int Lmu, int stride,
                                         const size_t (&off)[NR], const bool (&act)[NR],
                                         const cx<R> (&ph)[NR], cx<R> (&acc)[NR][4][3])
@@ -199,7 +217,7 @@ __device__ __forceinline__ void hop_dir(const DsArgs<S> &a, int site, int cmu, i
         const R bf = wrap ? (R)a.g.bcf[MU] : (R)1;
         if (bf != (R)0) {
             cx<R> u[3][3];
-            load_link<S, R>(a.U, MU, Vp, (unsigned)site, u);
+            load_link<S, R, REC>(a.U, MU, Vp, (unsigned)site, u);
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 if (!act[r]) continue;
@@ -233,7 +251,7 @@ __device__ __forceinline__ void hop_dir(const DsArgs<S> &a, int site, int cmu, i
         const R bf = wrap ? (R)a.g.bcf[MU] : (R)1;
         if (bf != (R)0) {
             cx<R> u[3][3];
-            load_link<S, R>(a.U, MU, Vp, (unsigned)j, u);
+            load_link<S, R, REC>(a.U, MU, Vp, (unsigned)j, u);
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 if (!act[r]) continue;
@@ -322,7 +340,7 @@ __device__ __forceinline__ int dslash_site(const Geo &g, int order, int xcd_rema
 // Q > 1: the Q sub-waves load the same link addresses in one instruction, so
 // a link line is fetched once for Q NR right-hand sides while every lane keeps
 // the registers of NR.
-template <class S, int NR, int Q, bool HW, bool EPI>
+template <class S, int NR, int Q, bool HW, bool EPI, bool REC>
 __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
 {
     using R = typename StoreT<S>::real;
@@ -379,10 +397,10 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[r][sp][c] = cmk((R)0, (R)0);
 
-    hop_dir<0, NR, S, R>(a, site, xc, g.Lx, 1, off, act, ph, acc);
-    hop_dir<1, NR, S, R>(a, site, yc, g.Ly, g.Lx, off, act, ph, acc);
-    hop_dir<2, NR, S, R>(a, site, zc, g.Lz, g.Lxy, off, act, ph, acc);
-    hop_dir<3, NR, S, R>(a, site, tc, g.Lt, g.Lxyz, off, act, ph, acc);
+    hop_dir<0, NR, S, R, REC>(a, site, xc, g.Lx, 1, off, act, ph, acc);
+    hop_dir<1, NR, S, R, REC>(a, site, yc, g.Ly, g.Lx, off, act, ph, acc);
+    hop_dir<2, NR, S, R, REC>(a, site, zc, g.Lz, g.Lxy, off, act, ph, acc);
+    hop_dir<3, NR, S, R, REC>(a, site, tc, g.Lt, g.Lxyz, off, act, ph, acc);
 
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -409,7 +427,7 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
 //   m = z + Lz (ob + nob (tc + ntc rg))
 // with ob the 64-site block of the (x, y) plane, tc the t-chunk and rg the
 // group of W RHS.  Needs V % 64 == 0 (no padding); the launcher checks.
-template <class S, bool HW, bool EPI, int W>
+template <class S, bool HW, bool EPI, int W, bool REC>
 __global__ __launch_bounds__(64 * W) void k_dslash_tm(DsArgs<S> a)
 {
     using R = typename StoreT<S>::real;
@@ -446,7 +464,7 @@ __global__ __launch_bounds__(64 * W) void k_dslash_tm(DsArgs<S> a)
     cx<R> pm[4][3], pc[4][3], pn[4][3], utm[3][3];
     load_spinor<S, R>(x, Vp, (unsigned)site_at(tm1), pm);
     load_spinor<S, R>(x, Vp, (unsigned)site_at(t0), pc);
-    load_link<S, R>(a.U, 3, Vp, (unsigned)site_at(tm1), utm);
+    load_link<S, R, REC>(a.U, 3, Vp, (unsigned)site_at(tm1), utm);
 
     const size_t offs[1] = {off};
     const bool acts[1] = {true};
@@ -457,7 +475,7 @@ __global__ __launch_bounds__(64 * W) void k_dslash_tm(DsArgs<S> a)
         const int tp1 = (t == g.Lt - 1) ? 0 : t + 1;
         load_spinor<S, R>(x, Vp, (unsigned)site_at(tp1), pn);
         cx<R> utc[3][3];
-        load_link<S, R>(a.U, 3, Vp, (unsigned)site, utc);
+        load_link<S, R, REC>(a.U, 3, Vp, (unsigned)site, utc);
         const cx<double> pd = a.phase[grp * g.Lt + t];
         const cx<R> ph[1] = {cmk((R)pd.x, (R)pd.y)};
 
@@ -467,9 +485,9 @@ __global__ __launch_bounds__(64 * W) void k_dslash_tm(DsArgs<S> a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[0][sp][c] = cmk((R)0, (R)0);
 
-        hop_dir<0, 1, S, R>(a, site, xc, g.Lx, 1, offs, acts, ph, acc);
-        hop_dir<1, 1, S, R>(a, site, yc, g.Ly, g.Lx, offs, acts, ph, acc);
-        hop_dir<2, 1, S, R>(a, site, z, g.Lz, g.Lxy, offs, acts, ph, acc);
+        hop_dir<0, 1, S, R, REC>(a, site, xc, g.Lx, 1, offs, acts, ph, acc);
+        hop_dir<1, 1, S, R, REC>(a, site, yc, g.Ly, g.Lx, offs, acts, ph, acc);
+        hop_dir<2, 1, S, R, REC>(a, site, z, g.Lz, g.Lxy, offs, acts, ph, acc);
 
         // time hops from registers
         {
@@ -543,13 +561,16 @@ static hipError_t launch_tm_w(const DsArgs<S> &a, bool hw, bool epi, hipStream_t
     const long nblk = (long)a.g.Lz * nob * ntc * ((a.n + W - 1) / W);
     const long padded = (nblk + 7) / 8 * 8;
     if (padded > 0x7fffffffL) return hipErrorInvalidValue;
-    const dim3 blk(64 * W);
-    if (epi)
-        hipLaunchKernelGGL((k_dslash_tm<S, true, true, W>), dim3((unsigned)padded), blk, 0, st, b);
-    else if (hw)
-        hipLaunchKernelGGL((k_dslash_tm<S, true, false, W>), dim3((unsigned)padded), blk, 0, st, b);
-    else
-        hipLaunchKernelGGL((k_dslash_tm<S, false, false, W>), dim3((unsigned)padded), blk, 0, st, b);
+    const dim3 blk(64 * W), grid((unsigned)padded);
+    if (a.recon) {
+        if (epi) hipLaunchKernelGGL((k_dslash_tm<S, true, true, W, true>), grid, blk, 0, st, b);
+        else if (hw) hipLaunchKernelGGL((k_dslash_tm<S, true, false, W, true>), grid, blk, 0, st, b);
+        else hipLaunchKernelGGL((k_dslash_tm<S, false, false, W, true>), grid, blk, 0, st, b);
+    } else {
+        if (epi) hipLaunchKernelGGL((k_dslash_tm<S, true, true, W, false>), grid, blk, 0, st, b);
+        else if (hw) hipLaunchKernelGGL((k_dslash_tm<S, true, false, W, false>), grid, blk, 0, st, b);
+        else hipLaunchKernelGGL((k_dslash_tm<S, false, false, W, false>), grid, blk, 0, st, b);
+    }
     return hipGetLastError();
 }
 
@@ -559,6 +580,34 @@ static hipError_t launch_tm(const DsArgs<S> &a, bool hw, bool epi, int block, hi
 {
     if (block == 512) return launch_tm_w<S, 8>(a, hw, epi, st);
     return launch_tm_w<S, 4>(a, hw, epi, st);
+}
+
+// One site-parallel kernel: the three operator kinds (fused epilogue, H_w,
+// D_w) for a link format.  With an occupancy cap the kernel is allowed more
+// than the default 64 KiB of dynamic LDS (once per kernel).
+template <class S, int NR, int Q, bool REC>
+static hipError_t launch_site(const DsArgs<S> &b, bool hw, bool epi, dim3 grid, int block, size_t lds,
+                              hipStream_t st)
+{
+    const void *fn = epi  ? (const void *)k_dslash<S, NR, Q, true, true, REC>
+                     : hw ? (const void *)k_dslash<S, NR, Q, true, false, REC>
+                          : (const void *)k_dslash<S, NR, Q, false, false, REC>;
+    if (lds > 0) {
+        static bool raised[3] = {false, false, false};
+        const int ki = epi ? 0 : (hw ? 1 : 2);
+        if (!raised[ki]) {
+            const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e != hipSuccess) return e;
+            raised[ki] = true;
+        }
+    }
+    if (epi)
+        hipLaunchKernelGGL((k_dslash<S, NR, Q, true, true, REC>), grid, dim3(block), lds, st, b);
+    else if (hw)
+        hipLaunchKernelGGL((k_dslash<S, NR, Q, true, false, REC>), grid, dim3(block), lds, st, b);
+    else
+        hipLaunchKernelGGL((k_dslash<S, NR, Q, false, false, REC>), grid, dim3(block), lds, st, b);
+    return hipGetLastError();
 }
 
 template <class S, int NR, int Q>
@@ -585,29 +634,9 @@ static hipError_t launch_nr(const DsArgs<S> &a, bool hw, bool epi, int block, hi
         nbx = (nbx + 7) & ~7;
         b.xcd_remap = 1;
     }
-    dim3 grid(nbx, (a.n + NR * Q - 1) / (NR * Q));
-    if (lds > 0) {   // allow more than the default 64 KiB of dynamic LDS (once per kernel)
-        static bool raised[3] = {false, false, false};
-        const int ki = epi ? 0 : (hw ? 1 : 2);
-        if (!raised[ki]) {
-            hipError_t e;
-            if (epi) e = hipFuncSetAttribute((const void *)k_dslash<S, NR, Q, true, true>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            else if (hw) e = hipFuncSetAttribute((const void *)k_dslash<S, NR, Q, true, false>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            else e = hipFuncSetAttribute((const void *)k_dslash<S, NR, Q, false, false>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            if (e != hipSuccess) return e;
-            raised[ki] = true;
-        }
-    }
-    if (epi)
-        hipLaunchKernelGGL((k_dslash<S, NR, Q, true, true>), grid, dim3(block), lds, st, b);
-    else if (hw)
-        hipLaunchKernelGGL((k_dslash<S, NR, Q, true, false>), grid, dim3(block), lds, st, b);
-    else
-        hipLaunchKernelGGL((k_dslash<S, NR, Q, false, false>), grid, dim3(block), lds, st, b);
-    return hipGetLastError();
+    const dim3 grid(nbx, (a.n + NR * Q - 1) / (NR * Q));
+    if (a.recon) return launch_site<S, NR, Q, true>(b, hw, epi, grid, block, lds, st);
+    return launch_site<S, NR, Q, false>(b, hw, epi, grid, block, lds, st);
 }
 
 // split = Q sub-waves per wave (1, 2, 4, 8; Q > 1 with NR <= 2 only; Q = 8

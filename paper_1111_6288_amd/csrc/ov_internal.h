@@ -31,6 +31,7 @@ struct DsArgs {
     int xcd_remap;           // set by the launcher
     int stream_hint;         // 1: epilogue inputs and the output bypass cache retention (non-temporal)
     int cols;                // order 1: the slab is walked as `cols` y-columns, one after the other
+    int recon;               // 1: links are SU(3); read two rows and rebuild the third
 };
 
 template <class S>
@@ -76,6 +77,10 @@ hipError_t launch_unpack_spinor(const S *in, double2 *out, long fstride, const i
 template <class S>
 hipError_t launch_pack_links(const double2 *in, S *out, int V, int Vp, hipStream_t st);
 hipError_t launch_count_nonfinite(const double *p, long n, int *count, hipStream_t st);
+// max over the nl links of canonical complex128 [nl][3][3] of
+// max_a |u_2a - conj(u_0b u_1c - u_0c u_1b)|, as the bits of a non-negative
+// double atomically maxed into *out (which the caller clears).
+hipError_t launch_link_row3_dev(const double2 *U, long nl, unsigned long long *out, hipStream_t st);
 
 // ---------------------------------------------------------------- projection
 long proj_dot_chunk(long K);

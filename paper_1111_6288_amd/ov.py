@@ -78,6 +78,8 @@ def _load():
         "ov_set_stream": ([vp, vp], i),
         "ov_last_error": ([vp], C.c_char_p),
         "ov_upload_gauge": ([vp, vp], i),
+        "ov_set_link_reconstruct": ([vp, i], i),
+        "ov_get_link_format": ([vp, cp(i), cp(d)], i),
         "ov_set_fields": ([vp, i, cp(d), cp(d)], i),
         "ov_set_field_eta": ([vp, i, d, d], i),
         "ov_set_sign_params": ([vp, i, d, d, cp(d)], i),
@@ -121,7 +123,8 @@ EXPORTED = ("ov_create", "ov_destroy", "ov_set_stream", "ov_last_error", "ov_upl
             "ov_set_tuning", "ov_get_tuning", "ov_autotune", "ov_memory_used", "ov_set_graphs",
             "ov_set_site_order", "ov_set_occupancy", "ov_get_launch_config",
             "ov_set_launch_config", "ov_hw_eigensolve", "ov_dense_heev", "ov_multishift_cg",
-            "ov_dov_eigensolve", "ov_timeslice_norm2", "ov_correlator_deta")
+            "ov_dov_eigensolve", "ov_timeslice_norm2", "ov_correlator_deta", "ov_set_link_reconstruct",
+            "ov_get_link_format")
 
 
 def _ints(v):
@@ -219,6 +222,16 @@ class Context:
     # ------------------------------------------------------------ setup
     def upload_gauge(self, U):
         return self._chk(lib.ov_upload_gauge(self._h, _dev(U, (4, self.V, 3, 3), "U")))
+
+    def set_link_reconstruct(self, enable=True):
+        """Allow (default) or forbid the two-row SU(3) link kernels."""
+        return self._chk(lib.ov_set_link_reconstruct(self._h, 1 if enable else 0))
+
+    def link_format(self):
+        """(two-row kernels in use, measured max |u_2 - conj(u_0 x u_1)| of the links)."""
+        r, dev = C.c_int(0), C.c_double(0)
+        self._chk(lib.ov_get_link_format(self._h, C.byref(r), C.byref(dev)))
+        return bool(r.value), dev.value
 
     def set_fields(self, q, eta):
         q, eta = list(q), list(eta)
@@ -450,9 +463,11 @@ class Context:
 
     def load_tuning(self, path, prec, nrhs):
         """Apply the launch shapes recorded by autotune (one JSON object per line) for this
-        lattice, precision and batch size; returns the kinds applied (empty if none match)."""
+        lattice, precision, batch size and link format (records without a format match
+        either); returns the kinds applied (empty if none match)."""
         import json
         applied = []
+        two_row = self.link_format()[0]
         try:
             lines = open(path).read().splitlines()
         except OSError:
@@ -462,7 +477,8 @@ class Context:
                 continue
             e = json.loads(line)
             if (e.get("arch") != "gfx950" or tuple(e.get("L", ())) != self.L or e.get("prec") != PREC[prec]
-                    or e.get("nrhs") != int(nrhs) or e.get("kind") not in self._KIND):
+                    or e.get("nrhs") != int(nrhs) or e.get("kind") not in self._KIND
+                    or bool(e.get("two_row_links", two_row)) != two_row):
                 continue
             defaults = {"stream_hint": 0, "rhs_split": 1, "cols": 1}
             self.set_launch_config(prec, e["kind"], **{k: e.get(k, defaults.get(k)) for k in self._CFG

@@ -1,0 +1,159 @@
+"""GPU parity of the two link formats read by the dslash kernels.
+
+SU(3) links satisfy u_2 = conj(u_0 x u_1) (third row from the first two), so
+the kernels may read two rows and rebuild the third.  The upload measures how
+far the links are from that identity and picks the two-row kernels only when
+it holds to FP64 rounding.  These tests check the measurement, the choice,
+that both formats give the oracle's operator, and that a change of format
+also reaches the captured (hipGraph) pipelines.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import api
+
+pytestmark = pytest.mark.gpu
+MW = -1.5
+
+
+def _ov():
+    from paper_1111_6288_amd import ov
+    return ov
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300)
+
+
+def _row3_dev(U):
+    """Host value of max |u_2 - conj(u_0 x u_1)| over the links."""
+    M = U.reshape(-1, 3, 3)
+    return np.abs(M[:, 2, :] - np.conj(np.cross(M[:, 0, :], M[:, 1, :]))).max()
+
+
+def test_link_format_detection():
+    ov = _ov()
+    L, bc = (4, 4, 4, 6), (0, 0, 0, 1)
+    ctx = ov.Context(L, bc, MW)
+    assert ctx.link_format() == (False, -1.0)
+    U = synth.su3_links(L, 0.5, 3)
+    ctx.upload_gauge(_t(U))
+    rec, dev = ctx.link_format()
+    assert rec and dev <= 1e-14
+    assert abs(dev - _row3_dev(U)) <= 1e-16
+    # a perturbation of one entry of one link is found
+    bad = U.copy()
+    bad[2, 17, 2, 1] += 3e-9
+    ctx.upload_gauge(_t(bad))
+    rec, dev = ctx.link_format()
+    assert not rec and abs(dev - 3e-9) <= 1e-15
+    # U(3) (det != 1) and non-unitary links are not SU(3)
+    ctx.upload_gauge(_t(U * np.exp(0.1j)))
+    assert ctx.link_format()[0] is False
+    ctx.upload_gauge(_t(1.001 * U))
+    assert ctx.link_format()[0] is False
+    # the switch
+    ctx.upload_gauge(_t(U))
+    ctx.set_link_reconstruct(False)
+    assert ctx.link_format()[0] is False
+    ctx.set_link_reconstruct(True)
+    assert ctx.link_format()[0] is True
+    with pytest.raises(ov.OvError) as e:
+        ctx._chk(ov.lib.ov_set_link_reconstruct(ctx._h, 2))
+    assert e.value.code == ov.OV_EINVAL
+
+
+CASES = [((4, 4, 4, 4), (0, 0, 0, 1)), ((6, 4, 6, 10), (2, 0, 0, 2)), ((4, 6, 8, 8), (1, 2, 0, 0))]
+
+
+@pytest.mark.parametrize("L,bc", CASES)
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-14), ("fp32", 2e-6), ("bf16", 2e-2)])
+def test_both_formats_match_oracle(L, bc, prec, tol):
+    """SU(3) links through the two-row and the full kernels, every site order."""
+    U = synth.su3_links(L, 0.5, 41)
+    q, eta = (2 / 3, -1 / 3), (0.2, -0.4)
+    ctx = _ov().Context(L, bc, MW)
+    ctx.upload_gauge(_t(U))
+    ctx.set_fields(q, eta)
+    x = synth.gaussian_spinors(L, 6, 8)
+    f = [0, 1, 1, 0, 0, 1]
+    refs = {}
+    for j in range(6):
+        lat = api.Lattice(L, bc, MW, U, q[f[j]] * eta[f[j]])
+        refs[j] = (api.dslash(lat, x[j], 1), api.dslash(lat, x[j], 0))
+    orders = [0, 2] + ([1] if L[2] % 8 == 0 else []) + ([3] if L[3] % 8 == 0 else [])
+    for recon in (True, False):
+        ctx.set_link_reconstruct(recon)
+        assert ctx.link_format()[0] is recon
+        for order in orders:
+            ctx.set_site_order(prec, order)
+            for op, k in (("HW", 0), ("DW", 1)):
+                y = _np(ctx.dslash(_t(x), f, op=op, prec=prec))
+                for j in range(6):
+                    assert _rel(y[j], refs[j][k]) < tol, (recon, order, op, j)
+
+
+@pytest.mark.parametrize("split,nr", [(1, 1), (1, 4), (2, 2), (4, 1), (8, 1)])
+def test_full_links_every_rhs_split(split, nr):
+    """Links that are not SU(3) (a U(1) factor per link) through the full kernels."""
+    L, bc = (6, 4, 6, 10), (2, 0, 0, 2)
+    rng = np.random.default_rng(5)
+    U = synth.su3_links(L, 0.5, 9) * np.exp(1j * rng.uniform(-1, 1, (4, synth.volume(L), 1, 1)))
+    ctx = _ov().Context(L, bc, MW)
+    ctx.upload_gauge(_t(U))
+    ctx.set_fields((2 / 3,), (0.3,))
+    assert ctx.link_format()[0] is False
+    x = synth.gaussian_spinors(L, 9, 4)
+    lat = api.Lattice(L, bc, MW, U, 2 / 3 * 0.3)
+    for prec, tol in (("fp64", 1e-14), ("fp32", 2e-6)):
+        ctx.set_launch_config(prec, "dslash", rhs_per_thread=nr, block=128, rhs_split=split)
+        y = _np(ctx.dslash(_t(x), [0] * 9, prec=prec))
+        for j in (0, 4, 8):
+            assert _rel(y[j], api.dslash(lat, x[j], 1)) < tol, (prec, j)
+
+
+def test_format_change_reaches_captured_pipeline():
+    """sign_apply is captured into a graph after repeated calls; uploading links
+    of the other format must not replay kernels of the old one."""
+    L, bc = (4, 4, 4, 8), (2, 0, 0, 2)
+    U = synth.su3_links(L, 0.4, 12)
+    ov = _ov()
+    n, eps = 40, 1e-3
+    x = _t(synth.gaussian_spinors(L, 3, 2))
+
+    def fresh(Ul):
+        c = ov.Context(L, bc, MW)
+        c.upload_gauge(_t(Ul))
+        c.set_fields((2 / 3,), (0.1,))
+        c.set_sign_params(n, eps, 6.5)
+        return c
+
+    ctx = fresh(U)
+    assert ctx.link_format()[0]
+    for _ in range(4):
+        y0 = ctx.sign_apply(x, [0] * 3)
+    torch.cuda.synchronize()
+    # not SU(3): every link times a phase
+    Ub = U * np.exp(0.05j)
+    ctx.upload_gauge(_t(Ub))
+    assert not ctx.link_format()[0]
+    ref = _np(fresh(Ub).sign_apply(x, [0] * 3))
+    for _ in range(3):
+        y = _np(ctx.sign_apply(x, [0] * 3))
+        assert _rel(y, ref) < 1e-13
+    assert _rel(_np(y0), ref) > 1e-6   # the two link fields give different operators
+    # and back to SU(3) links
+    ctx.upload_gauge(_t(U))
+    assert ctx.link_format()[0]
+    for _ in range(3):
+        assert _rel(_np(ctx.sign_apply(x, [0] * 3)), _np(y0)) < 1e-13
