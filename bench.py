@@ -87,15 +87,17 @@ def synth_volume():
     return L[0] * L[1] * L[2] * L[3]
 
 
-def measured_traffic(prec, nrhs, tuned):
+def measured_traffic(prec, nrhs, tuned, two_row):
     """HBM bytes per launch of the Clenshaw kernel from committed rocprofv3 PMC runs, if they were
-    taken on the current kernel source in the same launch configuration."""
+    taken on the current kernel source in the same launch configuration and link format."""
     path = os.path.join(ROOT, "profiles", "clenshaw_dslash_24x48_108rhs_pmc.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
     if rec.get("source_hash") != kernel_source_hash() or rec.get("prec") != prec or rec.get("nrhs") != nrhs:
+        return None
+    if bool(rec.get("two_row_links")) != bool(two_row):
         return None
     rt = dict(rec.get("tuning") or {})
     rt.setdefault("cols", 1)
@@ -381,14 +383,16 @@ def main():
     avg_ms = ms / max(n_launch, 1)
     bytes_per_launch = by / max(n_launch, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic_bytes = measured_traffic("fp32", nrhs, tuned["clenshaw"])
+    two_row = ctx.link_format()[0]
+    traffic_bytes = measured_traffic("fp32", nrhs, tuned["clenshaw"], two_row)
     traffic = None if traffic_bytes is None else round(traffic_bytes / (avg_ms * 1e-3) / 1e9, 1)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "traffic_bytes_per_launch": traffic_bytes,
-                "kernel": ("k_dslash_tm<float2,HW,EPI,W> (t-marching dslash + fused Clenshaw epilogue)"
+                "kernel": ("k_dslash_tm<float2,HW,EPI,W,REC> (t-marching dslash + fused Clenshaw epilogue)"
                            if tuned["clenshaw"]["site_order"] == 2
-                           else "k_dslash<float2,NR,HW,EPI> (dslash + fused Clenshaw epilogue)"),
+                           else "k_dslash<float2,NR,Q,HW,EPI,REC> (dslash + fused Clenshaw epilogue)"),
+                "two_row_links": two_row,
                 "launches": n_launch, "avg_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": bytes_per_launch}
     kernels = {k: {"launches": v[0], "ms": round(v[1], 2), "GBps": round(v[2] / max(v[1], 1e-9) / 1e6, 1)}

@@ -446,8 +446,10 @@ int dslash_launch(ov_ctx *c, const Batch &b, const int *fgroup, const S *x, S *y
     HIPCHK(launch_dslash<S>(d, hw || epi, epi, nr, tu.block, split, c->stream));
     const double sb = sizeof(S);
     const int nex = (e1 ? 1 : 0) + (e2 ? 1 : 0) + (e3 ? 1 : 0);
+    // compulsory bytes: the links once (two rows of each when rebuilt), every
+    // input and epilogue field once, the output once
     prof_end(c, pi, epi ? PC_CLENSHAW : PC_DSLASH,
-             (double)c->g.V * (36.0 * sb + (double)b.n * 12.0 * sb * (2 + nex)));
+             (double)c->g.V * ((c->recon ? 24.0 : 36.0) * sb + (double)b.n * 12.0 * sb * (2 + nex)));
     return OV_OK;
 }
 
