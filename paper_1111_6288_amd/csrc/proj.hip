@@ -11,6 +11,8 @@
 // each workgroup reduces one K-chunk to a partial l x n block, then a fixed-
 // order pass sums the partials (deterministic).  Both use the matrix cores
 // (v_mfma_f64_16x16x4f64) with 16x16 tiles of (vector, RHS).
+#include <algorithm>
+
 #include "ov_device.h"
 #include "ov_internal.h"
 
@@ -24,10 +26,13 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // j + 16k, and D[i][j] lands in lane j + 16 (i mod 4), register i div 4; so
 // lane q, register r holds row 4r + q/16, column q%16.
 //
-// Workgroup = W waves (W = blockDim / 64, at most 8); it owns one K-chunk.
-// Wave w owns vector tiles w, w+W, ... (up to MT tiles) and all RHS tiles (up
-// to NT); the launcher picks W = ceil(tiles / MT).  Per MFMA step
-// lane q holds A[i = q%16][k = q/16] = V and B[k = q/16][j = q%16] = X.
+// Workgroup (c, y) = W waves (W = blockDim / 64) owns K-chunk c and the
+// vector tiles y W MT + w + W m (m < MT) of its waves w, with all RHS tiles
+// (up to NT).  The launcher takes W = 4 and MT = 2: at about 160 VGPRs three
+// waves fit per SIMD, so three such workgroups share a CU, where one
+// workgroup holding all 13 tiles of l = 200 (7 waves) would leave it at 7
+// waves.  Per MFMA step lane q holds A[i = q%16][k = q/16] = V and
+// B[k = q/16][j = q%16] = X.
 template <class S, int MT, int NT>
 __global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict__ V, int l, long vstride,
                                                        const S *__restrict__ X, long xstride,
@@ -53,9 +58,10 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict
     // per-lane row pointers
     const double2 *vp[MT];
     bool vok[MT];
+    const int tile0 = blockIdx.y * W * MT + wave;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
-        const int i = (wave + W * m) * 16 + row;
+        const int i = (tile0 + W * m) * 16 + row;
         vok[m] = i < l;
         vp[m] = V + (long)(vok[m] ? i : 0) * vstride;
     }
@@ -128,7 +134,7 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict
         for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = (wave + W * m) * 16 + 4 * r + kq;
+                const int i = (tile0 + W * m) * 16 + 4 * r + kq;
                 const int j = t * 16 + row;
                 if (i < l && j < n) pc[(long)j * l + i] = make_double2(cre[m][t][r], cim[m][t][r]);
             }
@@ -231,7 +237,8 @@ __global__ void k_mul_coef(const double2 *C, const double *w, int l, int n, doub
 // ------------------------------------------------------------------ launchers
 long proj_dot_chunk(long K)
 {
-    // split K so that about 1024 workgroups run (4 per CU); each chunk a multiple of 4
+    // split K into about 1024 chunks (each a multiple of 4); with the tile split
+    // along y that is 2048 workgroups for l = 200
     long c = (K + 1023) / 1024;
     c = (c + 3) & ~3L;
     if (c < 64) c = 64;
@@ -242,7 +249,9 @@ template <class S, int MT, int NT>
 static void launch_dot_mt(const double2 *V, int l, long vstride, const S *X, long xstride, const int *slots,
                           int n, int Vp, int g5x, long chunk, int nchunk, double2 *part, int waves, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_proj_dot_mfma<S, MT, NT>), dim3(nchunk), dim3(64 * waves), 0, st, V, l, vstride, X,
+    const int tiles = (l + 15) / 16;
+    const int ny = (tiles + waves * MT - 1) / (waves * MT);
+    hipLaunchKernelGGL((k_proj_dot_mfma<S, MT, NT>), dim3(nchunk, ny), dim3(64 * waves), 0, st, V, l, vstride, X,
                        xstride, slots, n, Vp, g5x, chunk, part);
 }
 
@@ -255,11 +264,11 @@ hipError_t launch_proj_dot(const double2 *V, int l, long vstride, const S *X, lo
     const long K = 12L * Vp;
     const long chunk = proj_dot_chunk(K);
     const int nchunk = (int)((K + chunk - 1) / chunk);
-    // two vector tiles per wave, as many waves as that takes (<= 8): few idle
-    // tile slots, and the accumulators leave room for two waves per SIMD
+    // two vector tiles per wave, up to four waves per workgroup, the
+    // remaining tiles in further workgroups along y
     const int tiles = (l + 15) / 16;
     const int mt = tiles >= 2 ? 2 : 1;
-    const int waves = (tiles + mt - 1) / mt;
+    const int waves = std::min(4, (tiles + mt - 1) / mt);
     const int nt = (n + 15) / 16;
 #define OV_DOT_CASE(M, N) \
     if (mt == M && nt == N) \
