@@ -52,7 +52,7 @@ SRC = (12, 0, 0, 24)
 def parse():
     p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=4)
+    p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--fp64-steps", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -104,6 +104,27 @@ def measured_traffic(prec, nrhs, tuned, two_row):
     if rt != tuned:
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def copy_bandwidth(torch, nbytes=4 << 30, reps=5):
+    """Best device bandwidth (bytes read + written per second) of a plain copy: the runtime's
+    device-to-device copy and torch's elementwise neg over the same buffers, timed with events."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    srcf, dstf = src.view(torch.float32), dst.view(torch.float32)
+    best = 0.0
+    for op in (lambda: dst.copy_(src), lambda: torch.neg(srcf, out=dstf)):
+        op()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            op()
+        e1.record()
+        e1.synchronize()
+        best = max(best, 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3))
+    del src, dst, srcf, dstf
+    torch.cuda.empty_cache()
+    return best
 
 
 def build_inputs(torch, ov, args):
@@ -332,6 +353,8 @@ def main():
         print(json.dumps({"error": "no GPU visible"}), flush=True)
         sys.exit(1)
 
+    copy_bw = copy_bandwidth(torch)
+    print(f"[bench] plain copy: {copy_bw / 1e9:.0f} GB/s (read + write)", file=sys.stderr, flush=True)
     print(f"[bench] building inputs: L={L}, n={args.npoly}, l={args.lsmall}", file=sys.stderr, flush=True)
     ctx, U, x, fields, masses, t_setup = build_inputs(torch, ov, args)
     nrhs = len(fields)
@@ -388,6 +411,7 @@ def main():
     traffic = None if traffic_bytes is None else round(traffic_bytes / (avg_ms * 1e-3) / 1e9, 1)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "copy_GBps": round(copy_bw / 1e9, 1), "frac_of_copy": round(achieved / (copy_bw / 1e9), 4),
                 "traffic": traffic, "traffic_bytes_per_launch": traffic_bytes,
                 "kernel": ("k_dslash_tm<float2,HW,EPI,W,REC> (t-marching dslash + fused Clenshaw epilogue)"
                            if tuned["clenshaw"]["site_order"] == 2
