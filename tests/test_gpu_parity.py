@@ -571,3 +571,27 @@ def test_workspace_reuse_across_precisions_keeps_padding_zero():
         assert np.isfinite(y).all(), prec
         for j in range(3):
             assert _rel(y[j], ref[j]) < tol, (prec, j)
+
+
+@pytest.mark.parametrize("l,nrhs", [(129, 37), (200, 17), (256, 48)])
+def test_sign_large_small_space(l, nrhs):
+    """Small spaces of more than 8 tiles of 16 vectors (the V^dag X kernel then spreads the
+    tiles over several workgroups per K-chunk), ragged l and RHS counts, against the oracle."""
+    L, bc = (4, 4, 4, 6), (2, 0, 0, 2)
+    U = synth.su3_links(L, 0.3, 61)
+    ctx = make_ctx(L, bc, U, (2 / 3,), (0.2,))
+    n = 30
+    eps = 0.5 / n ** 2   # bounded Chebyshev growth for any spectrum (random small space)
+    ctx.set_sign_params(n, eps, 6.5)
+    Vs = synth.random_orthonormal(L, l, 7 + l)
+    lam = np.linspace(-1, 1, l)
+    ctx.upload_eigvecs(0, _t(Vs), lam)
+    x = synth.gaussian_spinors(L, nrhs, 3)
+    lat = api.Lattice(L, bc, MW, U, 2 / 3 * 0.2)
+    sp = api.SignParams(n, eps, 6.5, Vs, lam)
+    y64 = _np(ctx.sign_apply(_t(x), [0] * nrhs, prec="fp64"))
+    y32 = _np(ctx.sign_apply(_t(x), [0] * nrhs, prec="fp32"))
+    for j in sorted({0, nrhs // 2, nrhs - 1}):
+        ref = api.sign(lat, sp, x[j])
+        assert _rel(y64[j], ref) < 1e-12, (j, _rel(y64[j], ref))
+        assert _rel(y32[j], ref) < 2e-5, (j, _rel(y32[j], ref))
