@@ -101,6 +101,7 @@ def measured_traffic(prec, nrhs, tuned, two_row):
         return None
     rt = dict(rec.get("tuning") or {})
     rt.setdefault("cols", 1)
+    rt.setdefault("wshare", 1)
     if rt != tuned:
         return None
     return rec.get("hbm_bytes_per_launch")
@@ -415,6 +416,8 @@ def main():
                 "traffic": traffic, "traffic_bytes_per_launch": traffic_bytes,
                 "kernel": ("k_dslash_tm<float2,HW,EPI,W,REC> (t-marching dslash + fused Clenshaw epilogue)"
                            if tuned["clenshaw"]["site_order"] == 2
+                           else "k_dslash_lds<float2,NR,Q,HW,EPI,REC> (dslash with LDS-shared links + fused "
+                                "Clenshaw epilogue)" if tuned["clenshaw"].get("wshare", 1) > 1
                            else "k_dslash<float2,NR,Q,HW,EPI,REC> (dslash + fused Clenshaw epilogue)"),
                 "two_row_links": two_row,
                 "launches": n_launch, "avg_ms": round(avg_ms, 4),

@@ -421,10 +421,15 @@ int ov_set_occupancy(ov_ctx *ctx, int prec, int blocks_per_cu);
  * each link is fetched once per Q * rhs_per_thread RHS.  cols (a divisor of
  * Ly; site order 1 only) walks each XCD's z-slab as cols y-columns one after
  * the other, which shortens the distance between a site and its t
- * neighbours in the walk.  Set: OV_EINVAL on a value out of range (nothing
- * changed). */
-int ov_get_launch_config(ov_ctx *ctx, int prec, int kind, int cfg[7]);
-int ov_set_launch_config(ov_ctx *ctx, int prec, int kind, const int cfg[7]);
+ * neighbours in the walk.  wshare W in {1, 2, 4, 8}: with W > 1 (rhs_per_thread
+ * <= 2, rhs_split <= 4) a workgroup is W waves that cover the same 64/Q sites
+ * for W different groups of Q * rhs_per_thread RHS; the workgroup copies the
+ * links of its sites into LDS once and every wave reads them there, so a link
+ * is fetched once per W * Q * rhs_per_thread RHS (block is then unused; the
+ * t-marching order ignores wshare).  ov_set_tuning resets wshare to 1.  Set:
+ * OV_EINVAL on a value out of range (nothing changed). */
+int ov_get_launch_config(ov_ctx *ctx, int prec, int kind, int cfg[8]);
+int ov_set_launch_config(ov_ctx *ctx, int prec, int kind, const int cfg[8]);
 int ov_autotune(ov_ctx *ctx, int prec, int nrhs, const char *cache_path);
 
 /*

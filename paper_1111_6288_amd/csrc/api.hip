@@ -95,7 +95,7 @@ struct ov_ctx {
 
     // dslash launch shape per precision and kind (0: plain, 1: fused Clenshaw epilogue)
     struct Launch {
-        int nr = 2, block = 128, order = 0, cap = 0, stream_hint = 0, split = 1, cols = 1;
+        int nr = 2, block = 128, order = 0, cap = 0, stream_hint = 0, split = 1, cols = 1, wshare = 1;
     };
     Launch tune[3][2];
 
@@ -439,9 +439,11 @@ int dslash_launch(ov_ctx *c, const Batch &b, const int *fgroup, const S *x, S *y
         int nch = (int)std::max(1L, std::min((long)c->g.Lt / 4, (4096 + per_chunk - 1) / per_chunk));
         d.tchunk = (c->g.Lt + nch - 1) / nch;
     }
-    int nr = tu.nr, split = tu.split;
+    int nr = tu.nr, split = tu.split, ws = tu.wshare;
     while (split > 1 && (split / 2) * nr >= b.n) split /= 2;
     while (nr > 1 && nr / 2 >= b.n) nr /= 2;
+    while (ws > 1 && (ws / 2) * split * nr >= b.n) ws /= 2;   // no wave without a RHS
+    d.wshare = ws;
     int pi = prof_begin(c);
     HIPCHK(launch_dslash<S>(d, hw || epi, epi, nr, tu.block, split, c->stream));
     const double sb = sizeof(S);
@@ -1194,6 +1196,7 @@ int ov_set_tuning(ov_ctx *c, int prec, int rhs_per_thread, int block)
     for (auto &tu : c->tune[prec]) {
         tu.nr = rhs_per_thread;
         tu.block = block;
+        tu.wshare = 1;
         if (rhs_per_thread > 2) tu.split = 1;
     }
     return OV_OK;
@@ -1233,6 +1236,7 @@ int ov_get_launch_config(ov_ctx *c, int prec, int kind, int *cfg)
     cfg[4] = tu.stream_hint;
     cfg[5] = tu.split;
     cfg[6] = tu.cols;
+    cfg[7] = tu.wshare;
     return OV_OK;
 }
 
@@ -1243,6 +1247,7 @@ int ov_set_launch_config(ov_ctx *c, int prec, int kind, const int *cfg)
     if (kind != 0 && kind != 1) return fail(c, OV_EINVAL, "kind must be 0 (plain) or 1 (fused epilogue)");
     if (!cfg) return fail(c, OV_EINVAL, "cfg is NULL");
     const int nr = cfg[0], bl = cfg[1], od = cfg[2], cp = cfg[3], sh = cfg[4], sp = cfg[5], cl = cfg[6];
+    const int ws = cfg[7];
     if (nr != 1 && nr != 2 && nr != 4 && nr != 8) return fail(c, OV_EINVAL, "rhs_per_thread must be 1, 2, 4 or 8");
     if (bl != 64 && bl != 128 && bl != 192 && bl != 256 && bl != 512)
         return fail(c, OV_EINVAL, "block must be 64, 128, 192, 256 or 512");
@@ -1253,6 +1258,8 @@ int ov_set_launch_config(ov_ctx *c, int prec, int kind, const int *cfg)
     if (sp == 8 && prec == OV_BF16) return fail(c, OV_EINVAL, "rhs_split 8 is for FP64 and FP32 storage");
     if (sp > 1 && nr > 2) return fail(c, OV_EINVAL, "rhs_split > 1 needs rhs_per_thread <= 2");
     if (cl < 1 || cl > 64 || c->g.Ly % cl != 0) return fail(c, OV_EINVAL, "cols must divide Ly (%d)", c->g.Ly);
+    if (ws != 1 && ws != 2 && ws != 4 && ws != 8) return fail(c, OV_EINVAL, "wshare must be 1, 2, 4 or 8");
+    if (ws > 1 && (nr > 2 || sp > 4)) return fail(c, OV_EINVAL, "wshare > 1 needs rhs_per_thread <= 2 and rhs_split <= 4");
     invalidate_graphs(c);
     auto &tu = c->tune[prec][kind];
     tu.nr = nr;
@@ -1262,6 +1269,7 @@ int ov_set_launch_config(ov_ctx *c, int prec, int kind, const int *cfg)
     tu.stream_hint = sh;
     tu.split = sp;
     tu.cols = cl;
+    tu.wshare = ws;
     return OV_OK;
 }
 
@@ -1833,7 +1841,7 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e9));
         const int nrs[4] = {1, 2, 4, 8}, blks[4] = {64, 128, 256, 512};
-        const int caps[3] = {0, 2, 4}, splits[4] = {1, 2, 4, 8}, colss[3] = {1, 2, 4};
+        const int caps[3] = {0, 2, 4}, splits[4] = {1, 2, 4, 8}, colss[3] = {1, 2, 4}, wss[4] = {1, 2, 4, 8};
         const int reps = 3;
         const bool was = c->prof_on;
         c->prof_on = false;
@@ -1855,7 +1863,9 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
             for (int cl : colss)
             for (int cp : caps)
             for (int sp : splits)
+            for (int ws : wss)
             for (int nr : nrs) {
+                if (ws > 1 && (od == 2 || nr > 2 || sp > 4 || (ws / 2) * sp * nr >= nrhs)) continue;
                 if (cl > 1 && (od != 1 || c->g.Ly % cl != 0)) continue;
                 if (sp > 1 && (nr > 2 || od == 2)) continue;
                 if (sp > 1 && (sp / 2) * nr >= nrhs) continue;
@@ -1866,6 +1876,7 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
                 if (nr > 1 && nr / 2 >= nrhs) continue;
                 if (prec == OV_FP64 && nr == 8) continue;
                 for (int bl : blks) {
+                    if (ws > 1 && bl != (ws == 8 ? 256 : 64 * ws)) continue;   // link sharing: one pass, block unused
                     if (od != 2 && bl == 512) continue;   // 512 threads: t-marching only
                     if (od == 2 && bl < 256) continue;    // t-marching: 4 or 8 RHS per workgroup
                     if (od == 2 && bl == 512 && prec == OV_FP64) continue;   // FP64 needs > 256 VGPRs
@@ -1876,6 +1887,7 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
                     tu.stream_hint = sh;
                     tu.split = sp;
                     tu.cols = cl;
+                    tu.wshare = ws;
                     if (rc == OV_OK) rc = launch();
                     if (rc == OV_OK && hipEventRecord(e0, c->stream) != hipSuccess) rc = OV_EHIP;
                     for (int rep = 0; rep < reps && rc == OV_OK; ++rep) rc = launch();
@@ -1907,9 +1919,9 @@ int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
                                  "{\"arch\": \"gfx950\", \"L\": [%d, %d, %d, %d], \"prec\": %d, \"nrhs\": %d, "
                                  "\"kind\": \"%s\", \"rhs_per_thread\": %d, \"block\": %d, \"site_order\": %d, "
                                  "\"blocks_per_cu\": %d, \"stream_hint\": %d, \"rhs_split\": %d, \"cols\": %d, "
-                                 "\"two_row_links\": %d, \"ms_per_launch\": %.6f}\n",
+                                 "\"wshare\": %d, \"two_row_links\": %d, \"ms_per_launch\": %.6f}\n",
                                  c->L[0], c->L[1], c->L[2], c->L[3], prec, nrhs, kind ? "clenshaw" : "dslash",
-                                 tu.nr, tu.block, tu.order, tu.cap, tu.stream_hint, tu.split, tu.cols,
+                                 tu.nr, tu.block, tu.order, tu.cap, tu.stream_hint, tu.split, tu.cols, tu.wshare,
                                  c->recon ? 1 : 0, best_ms[kind]);
                 }
                 std::fclose(fp);

@@ -135,6 +135,17 @@ __device__ __forceinline__ void stpair_nt(S *__restrict__ f, int Vp, int p, unsi
 // gauge upload measures how far the stored links are from it and selects
 // these kernels only where it holds to FP64 rounding; they read two thirds of
 // the link bytes.
+template <class R>
+__device__ __forceinline__ void rebuild_row2(cx<R> (&u)[3][3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int b1 = (a + 1) % 3, c1 = (a + 2) % 3;
+        const cx<R> t = csub(cmul(u[0][b1], u[1][c1]), cmul(u[0][c1], u[1][b1]));
+        u[2][a] = cmk(t.x, -t.y);
+    }
+}
+
 template <class S, class R, bool REC>
 __device__ __forceinline__ void load_link(const S *__restrict__ U, int mu, int Vp, unsigned s, cx<R> (&u)[3][3])
 {
@@ -143,12 +154,7 @@ __device__ __forceinline__ void load_link(const S *__restrict__ U, int mu, int V
 #pragma unroll
         for (int p = 0; p < 3; ++p)
             ldpair<S, R>(b, Vp, p, s, u[(2 * p) / 3][(2 * p) % 3], u[(2 * p + 1) / 3][(2 * p + 1) % 3]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int b1 = (a + 1) % 3, c1 = (a + 2) % 3;
-            const cx<R> t = csub(cmul(u[0][b1], u[1][c1]), cmul(u[0][c1], u[1][b1]));
-            u[2][a] = cmk(t.x, -t.y);
-        }
+        rebuild_row2(u);
     } else {
 #pragma unroll
         for (int p = 0; p < 4; ++p)
@@ -203,10 +209,37 @@ __device__ __forceinline__ void write_site(const DsArgs<S> &a, size_t off, unsig
     }
 }
 
+// Where hop_dir takes its links from.  Slot mu is U_mu(s) (forward hop),
+// slot 4 + mu is U_mu(s - mu) (backward hop); `site` is the site whose link
+// is wanted (s or s - mu).
+template <class S, class R, bool REC>
+struct GlobalLinks {   // straight from the packed link field
+    const S *U;
+    int Vp;
+    __device__ __forceinline__ void operator()(int mu, int, unsigned site, cx<R> (&u)[3][3]) const
+    {
+        load_link<S, R, REC>(U, mu, Vp, site, u);
+    }
+};
+
+template <class R, bool REC, int SL>
+struct LdsLinks {   // staged in LDS by the workgroup: [slot][component][site slot], SL site slots
+    const cx<R> *base;
+    int sl;   // this thread's site slot
+    __device__ __forceinline__ void operator()(int, int slot, unsigned, cx<R> (&u)[3][3]) const
+    {
+        constexpr int E = REC ? 6 : 9;
+        const cx<R> *p = base + slot * E * SL + sl;
+#pragma unroll
+        for (int k = 0; k < E; ++k) u[k / 3][k % 3] = p[k * SL];
+        if constexpr (REC) rebuild_row2(u);
+    }
+};
+
 // One direction, both hops, for all NR right-hand sides of this thread.
-template <int MU, int NR, class S, class R, bool REC>
-__device__ __forceinline__ void hop_dir(const DsArgs<S> &a, int site, int cmu, int Lmu, int stride,
-                                        const size_t (&off)[NR], const bool (&act)[NR],
+template <int MU, int NR, class S, class R, class LF>
+__device__ __forceinline__ void hop_dir(const DsArgs<S> &a, const LF &links, int site, int cmu, int Lmu,
+                                        int stride, const size_t (&off)[NR], const bool (&act)[NR],
                                         const cx<R> (&ph)[NR], cx<R> (&acc)[NR][4][3])
 {
     const int Vp = a.g.Vp;
@@ -217,7 +250,7 @@ __device__ __forceinline__ void hop_dir(const DsArgs<S> &a, int site, int cmu, i
         const R bf = wrap ? (R)a.g.bcf[MU] : (R)1;
         if (bf != (R)0) {
             cx<R> u[3][3];
-            load_link<S, R, REC>(a.U, MU, Vp, (unsigned)site, u);
+            links(MU, MU, (unsigned)site, u);
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 if (!act[r]) continue;
@@ -251,7 +284,7 @@ __device__ __forceinline__ void hop_dir(const DsArgs<S> &a, int site, int cmu, i
         const R bf = wrap ? (R)a.g.bcf[MU] : (R)1;
         if (bf != (R)0) {
             cx<R> u[3][3];
-            load_link<S, R, REC>(a.U, MU, Vp, (unsigned)j, u);
+            links(MU, 4 + MU, (unsigned)j, u);
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 if (!act[r]) continue;
@@ -302,13 +335,11 @@ __device__ __forceinline__ int xcd_block(int b, int nblk)
 // two boundary slices of a slab read neighbours another XCD fetched (2/(Lt/8)
 // per site, against 2/(Lz/8) for order 1).  orders 1 and 3 need Lz % 8 == 0
 // (Lt % 8 == 0) and V % 64 == 0 (no padding); the launcher checks.
-template <int Q>
-__device__ __forceinline__ int dslash_site(const Geo &g, int order, int xcd_remap, int cols)
+//
+// site_in_block gives the site of position tb (0 <= tb < spb) in workgroup
+// blockIdx.x when every workgroup covers spb sites.
+__device__ __forceinline__ int site_in_block(const Geo &g, int order, int xcd_remap, int cols, int tb, int spb)
 {
-    constexpr int SL = 64 / Q;   // sites per wave
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int spb = (int)(blockDim.x >> 6) * SL;
-    const int tb = wave * SL + (lane & (SL - 1));
     if (order == 3) {
         const int xcd = blockIdx.x & 7;
         const int u = (blockIdx.x >> 3) * spb + tb;
@@ -335,6 +366,16 @@ __device__ __forceinline__ int dslash_site(const Geo &g, int order, int xcd_rema
     }
     const int blk = xcd_remap ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
     return blk * spb + tb;
+}
+
+template <int Q>
+__device__ __forceinline__ int dslash_site(const Geo &g, int order, int xcd_remap, int cols)
+{
+    constexpr int SL = 64 / Q;   // sites per wave
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int spb = (int)(blockDim.x >> 6) * SL;
+    const int tb = wave * SL + (lane & (SL - 1));
+    return site_in_block(g, order, xcd_remap, cols, tb, spb);
 }
 
 // Q > 1: the Q sub-waves load the same link addresses in one instruction, so
@@ -397,10 +438,123 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[r][sp][c] = cmk((R)0, (R)0);
 
-    hop_dir<0, NR, S, R, REC>(a, site, xc, g.Lx, 1, off, act, ph, acc);
-    hop_dir<1, NR, S, R, REC>(a, site, yc, g.Ly, g.Lx, off, act, ph, acc);
-    hop_dir<2, NR, S, R, REC>(a, site, zc, g.Lz, g.Lxy, off, act, ph, acc);
-    hop_dir<3, NR, S, R, REC>(a, site, tc, g.Lt, g.Lxyz, off, act, ph, acc);
+    const GlobalLinks<S, R, REC> lf{a.U, g.Vp};
+    hop_dir<0, NR, S, R>(a, lf, site, xc, g.Lx, 1, off, act, ph, acc);
+    hop_dir<1, NR, S, R>(a, lf, site, yc, g.Ly, g.Lx, off, act, ph, acc);
+    hop_dir<2, NR, S, R>(a, lf, site, zc, g.Lz, g.Lxy, off, act, ph, acc);
+    hop_dir<3, NR, S, R>(a, lf, site, tc, g.Lt, g.Lxyz, off, act, ph, acc);
+
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (!act[r]) continue;
+        cx<R> p[4][3];
+        load_spinor<S, R>(a.x + off[r], g.Vp, (unsigned)site, p);
+        write_site<S, R, HW, EPI>(a, off[r], (unsigned)site, p, acc[r]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Link-sharing variant.  The W waves of a workgroup (W = blockDim / 64: 2, 4
+// or 8) cover the same 64/Q sites, each for its own Q NR right-hand sides, so
+// a workgroup covers 64/Q sites for W Q NR RHS.  Before the stencil the
+// workgroup copies the eight links its sites use (U_mu(s) and U_mu(s - mu),
+// two or three rows each) into LDS; every wave then reads them there, so a
+// link crosses HBM once per W Q NR RHS rather than once per Q NR, without
+// narrowing the run of consecutive sites each load instruction covers.
+// Threads of padding sites take part in the copy and the barrier and only
+// then leave.
+template <class S, int NR, int Q, bool HW, bool EPI, bool REC>
+__global__ __launch_bounds__(512) void k_dslash_lds(DsArgs<S> a)
+{
+    using R = typename StoreT<S>::real;
+    constexpr int SL = 64 / Q, E = REC ? 6 : 9;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    cx<R> *lk = reinterpret_cast<cx<R> *>(lds_raw);   // [8][E][SL]
+    const Geo &g = a.g;
+    const int W = (int)(blockDim.x >> 6), wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+
+    for (int idx = (int)threadIdx.x; idx < 8 * SL; idx += (int)blockDim.x) {
+        const int slot = idx / SL, sl = idx - slot * SL;
+        const int s = site_in_block(g, a.order, a.xcd_remap, a.cols, sl, SL);
+        cx<R> *dst = lk + slot * E * SL + sl;
+        if (s >= g.V) {   // padding or beyond the slab: never read
+#pragma unroll
+            for (int k = 0; k < E; ++k) dst[k * SL] = cmk((R)0, (R)0);
+            continue;
+        }
+        const int mu = slot & 3;
+        int src = s;
+        if (slot >= 4) {   // backward neighbour s - mu, wrapping
+            int c, L, stride;
+            if (mu == 0) { c = s % g.Lx; L = g.Lx; stride = 1; }
+            else if (mu == 1) { c = (s / g.Lx) % g.Ly; L = g.Ly; stride = g.Lx; }
+            else if (mu == 2) { c = (s / g.Lxy) % g.Lz; L = g.Lz; stride = g.Lxy; }
+            else { c = s / g.Lxyz; L = g.Lt; stride = g.Lxyz; }
+            src = (c == 0) ? s + (L - 1) * stride : s - stride;
+        }
+#pragma unroll
+        for (int k = 0; k < E; ++k) dst[k * SL] = ldc<R>(a.U, lpos<S>(mu, k, src, g.Vp));
+    }
+    __syncthreads();
+
+    const int sl = lane & (SL - 1);
+    const int site = site_in_block(g, a.order, a.xcd_remap, a.cols, sl, SL);
+    if (site >= g.Vp) return;
+    const int sub = lane / SL;
+    const int j0 = ((blockIdx.y * W + wave) * Q + sub) * NR;
+
+    size_t off[NR];
+    bool act[NR];
+    int grp[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int j = j0 + r;
+        act[r] = j < a.n;
+        const int jj = act[r] ? j : 0;
+        int s = a.slots ? a.slots[jj] : jj;
+        if (Q == 1) s = __builtin_amdgcn_readfirstlane(s);   // uniform: depends on blockIdx.y and the wave
+        off[r] = (size_t)s * (size_t)a.fstride;
+        int gr = a.fgroup ? a.fgroup[s] : 0;
+        if (Q == 1) gr = __builtin_amdgcn_readfirstlane(gr);
+        grp[r] = gr;
+    }
+    if (site >= g.V) {   // padding sites hold zeros in every field
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (!act[r]) continue;
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                stpair<S, R>(a.y + off[r], g.Vp, q, (unsigned)site, cmk((R)0, (R)0), cmk((R)0, (R)0));
+        }
+        return;
+    }
+
+    int rem = site;
+    const int xc = rem % g.Lx; rem /= g.Lx;
+    const int yc = rem % g.Ly; rem /= g.Ly;
+    const int zc = rem % g.Lz;
+    const int tc = rem / g.Lz;
+
+    cx<R> ph[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const cx<double> p = a.phase[grp[r] * g.Lt + tc];
+        ph[r] = cmk((R)p.x, (R)p.y);
+    }
+
+    cx<R> acc[NR][4][3];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[r][sp][c] = cmk((R)0, (R)0);
+
+    const LdsLinks<R, REC, SL> lf{lk, sl};
+    hop_dir<0, NR, S, R>(a, lf, site, xc, g.Lx, 1, off, act, ph, acc);
+    hop_dir<1, NR, S, R>(a, lf, site, yc, g.Ly, g.Lx, off, act, ph, acc);
+    hop_dir<2, NR, S, R>(a, lf, site, zc, g.Lz, g.Lxy, off, act, ph, acc);
+    hop_dir<3, NR, S, R>(a, lf, site, tc, g.Lt, g.Lxyz, off, act, ph, acc);
 
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -485,9 +639,10 @@ __global__ __launch_bounds__(64 * W) void k_dslash_tm(DsArgs<S> a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[0][sp][c] = cmk((R)0, (R)0);
 
-        hop_dir<0, 1, S, R, REC>(a, site, xc, g.Lx, 1, offs, acts, ph, acc);
-        hop_dir<1, 1, S, R, REC>(a, site, yc, g.Ly, g.Lx, offs, acts, ph, acc);
-        hop_dir<2, 1, S, R, REC>(a, site, z, g.Lz, g.Lxy, offs, acts, ph, acc);
+        const GlobalLinks<S, R, REC> lf{a.U, Vp};
+        hop_dir<0, 1, S, R>(a, lf, site, xc, g.Lx, 1, offs, acts, ph, acc);
+        hop_dir<1, 1, S, R>(a, lf, site, yc, g.Ly, g.Lx, offs, acts, ph, acc);
+        hop_dir<2, 1, S, R>(a, lf, site, z, g.Lz, g.Lxy, offs, acts, ph, acc);
 
         // time hops from registers
         {
@@ -639,6 +794,59 @@ static hipError_t launch_nr(const DsArgs<S> &a, bool hw, bool epi, int block, hi
     return launch_site<S, NR, Q, false>(b, hw, epi, grid, block, lds, st);
 }
 
+template <class S, int NR, int Q, bool REC>
+static hipError_t launch_lds_kernel(const DsArgs<S> &b, bool hw, bool epi, dim3 grid, int W, size_t lds,
+                                    hipStream_t st)
+{
+    const void *fn = epi  ? (const void *)k_dslash_lds<S, NR, Q, true, true, REC>
+                     : hw ? (const void *)k_dslash_lds<S, NR, Q, true, false, REC>
+                          : (const void *)k_dslash_lds<S, NR, Q, false, false, REC>;
+    static bool raised[3] = {false, false, false};
+    const int ki = epi ? 0 : (hw ? 1 : 2);
+    if (!raised[ki]) {   // staged links of FP64 full links exceed the default 64 KiB
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        raised[ki] = true;
+    }
+    const dim3 blk(64 * W);
+    if (epi)
+        hipLaunchKernelGGL((k_dslash_lds<S, NR, Q, true, true, REC>), grid, blk, lds, st, b);
+    else if (hw)
+        hipLaunchKernelGGL((k_dslash_lds<S, NR, Q, true, false, REC>), grid, blk, lds, st, b);
+    else
+        hipLaunchKernelGGL((k_dslash_lds<S, NR, Q, false, false, REC>), grid, blk, lds, st, b);
+    return hipGetLastError();
+}
+
+// Link-sharing launch: W = a.wshare waves per workgroup on the same 64/Q
+// sites; LDS holds the staged links (more if the occupancy cap asks for it).
+template <class S, int NR, int Q>
+static hipError_t launch_lds(const DsArgs<S> &a, bool hw, bool epi, hipStream_t st)
+{
+    using R = typename StoreT<S>::real;
+    constexpr int SL = 64 / Q;
+    const int W = a.wshare;
+    const size_t need = (size_t)8 * (a.recon ? 6 : 9) * SL * sizeof(cx<R>);
+    const size_t capr = a.blocks_per_cu > 0 ? (size_t)(160 * 1024) / (size_t)a.blocks_per_cu - 256 : 0;
+    const size_t lds = need > capr ? need : capr;
+    int nbx = (a.g.Vp + SL - 1) / SL;
+    DsArgs<S> b = a;
+    b.xcd_remap = 0;
+    if (b.order == 1 && (a.g.Lz % 8 != 0 || a.g.V % 64 != 0)) b.order = 0;
+    if (b.cols < 1 || a.g.Ly % b.cols != 0) b.cols = 1;
+    if (b.order == 3 && (a.g.Lt % 8 != 0 || a.g.V % 64 != 0)) b.order = 0;
+    if (b.order == 2) b.order = 0;
+    if (b.order == 1 || b.order == 3) {
+        nbx = 8 * ((a.g.V / 8 + SL - 1) / SL);
+    } else if (nbx >= 64) {
+        nbx = (nbx + 7) & ~7;
+        b.xcd_remap = 1;
+    }
+    const dim3 grid(nbx, (a.n + NR * Q * W - 1) / (NR * Q * W));
+    if (a.recon) return launch_lds_kernel<S, NR, Q, true>(b, hw, epi, grid, W, lds, st);
+    return launch_lds_kernel<S, NR, Q, false>(b, hw, epi, grid, W, lds, st);
+}
+
 // split = Q sub-waves per wave (1, 2, 4, 8; Q > 1 with NR <= 2 only; Q = 8
 // keeps whole 128-byte lines per sub-wave for 16-byte elements only).
 template <class S>
@@ -647,6 +855,19 @@ hipError_t launch_dslash(const DsArgs<S> &a, bool hw, bool epi, int nr, int bloc
     if (a.n <= 0) return hipSuccess;
     if (block < 64 || block > 512 || (block & 63)) return hipErrorInvalidValue;
     if (a.order == 2 && a.g.V % 64 == 0) return launch_tm<S>(a, hw, epi, block, st);
+    if (a.wshare == 2 || a.wshare == 4 || a.wshare == 8) {   // waves share sites and staged links
+        if (nr == 1) {
+            if (split == 1) return launch_lds<S, 1, 1>(a, hw, epi, st);
+            if (split == 2) return launch_lds<S, 1, 2>(a, hw, epi, st);
+            if (split == 4) return launch_lds<S, 1, 4>(a, hw, epi, st);
+        } else if (nr == 2) {
+            if (split == 1) return launch_lds<S, 2, 1>(a, hw, epi, st);
+            if (split == 2) return launch_lds<S, 2, 2>(a, hw, epi, st);
+            if (split == 4) return launch_lds<S, 2, 4>(a, hw, epi, st);
+        }
+        return hipErrorInvalidValue;
+    }
+    if (a.wshare != 1) return hipErrorInvalidValue;
     if (block > 256) block = 256;   // wider workgroups only for the t-marching kernel
     if (split == 2 || split == 4) {
         if (nr == 1) return split == 2 ? launch_nr<S, 1, 2>(a, hw, epi, block, st) : launch_nr<S, 1, 4>(a, hw, epi, block, st);

@@ -32,6 +32,7 @@ struct DsArgs {
     int stream_hint;         // 1: epilogue inputs and the output bypass cache retention (non-temporal)
     int cols;                // order 1: the slab is walked as `cols` y-columns, one after the other
     int recon;               // 1: links are SU(3); read two rows and rebuild the third
+    int wshare;              // 1, or W = 2, 4, 8 waves per workgroup sharing sites and LDS-staged links
 };
 
 template <class S>

@@ -434,11 +434,11 @@ class Context:
         return self._chk(lib.ov_set_occupancy(self._h, PREC[prec], int(blocks_per_cu)))
 
     _KIND = {"dslash": 0, "clenshaw": 1}
-    _CFG = ("rhs_per_thread", "block", "site_order", "blocks_per_cu", "stream_hint", "rhs_split", "cols")
+    _CFG = ("rhs_per_thread", "block", "site_order", "blocks_per_cu", "stream_hint", "rhs_split", "cols", "wshare")
 
     def get_launch_config(self, prec, kind="dslash"):
         """Launch shape of the plain ("dslash") or fused-epilogue ("clenshaw") launches of prec."""
-        cfg = (C.c_int * 7)()
+        cfg = (C.c_int * len(self._CFG))()
         self._chk(lib.ov_get_launch_config(self._h, PREC[prec], self._KIND[kind], cfg))
         return dict(zip(self._CFG, list(cfg)))
 
@@ -449,7 +449,7 @@ class Context:
             if k not in cur:
                 raise KeyError(k)
             cur[k] = int(v)
-        arr = (C.c_int * 7)(*[cur[k] for k in self._CFG])
+        arr = (C.c_int * len(self._CFG))(*[cur[k] for k in self._CFG])
         return self._chk(lib.ov_set_launch_config(self._h, PREC[prec], self._KIND[kind], arr))
 
     def get_tuning(self, prec):
@@ -480,7 +480,7 @@ class Context:
                     or e.get("nrhs") != int(nrhs) or e.get("kind") not in self._KIND
                     or bool(e.get("two_row_links", two_row)) != two_row):
                 continue
-            defaults = {"stream_hint": 0, "rhs_split": 1, "cols": 1}
+            defaults = {"stream_hint": 0, "rhs_split": 1, "cols": 1, "wshare": 1}
             self.set_launch_config(prec, e["kind"], **{k: e.get(k, defaults.get(k)) for k in self._CFG
                                                        if k in e or k in defaults})
             applied.append(e["kind"])

@@ -157,3 +157,74 @@ def test_format_change_reaches_captured_pipeline():
     assert ctx.link_format()[0]
     for _ in range(3):
         assert _rel(_np(ctx.sign_apply(x, [0] * 3)), _np(y0)) < 1e-13
+
+
+SHARE_CASES = [((6, 4, 6, 10), (2, 0, 0, 2)), ((4, 6, 8, 8), (1, 2, 0, 0))]
+
+
+@pytest.mark.parametrize("L,bc", SHARE_CASES)
+@pytest.mark.parametrize("wshare", [2, 4, 8])
+@pytest.mark.parametrize("nr,split", [(1, 1), (1, 2), (1, 4), (2, 2), (2, 1)])
+def test_link_sharing_workgroups(L, bc, wshare, nr, split):
+    """Waves of a workgroup on the same sites with the links staged in LDS: every
+    precision, site order and link format against the oracle; 13 RHS leave
+    partial groups and ragged volumes leave padding sites."""
+    U = synth.su3_links(L, 0.5, 43)
+    q, eta = (2 / 3, -1 / 3), (0.25, -0.5)
+    ctx = _ov().Context(L, bc, MW)
+    ctx.upload_gauge(_t(U))
+    ctx.set_fields(q, eta)
+    nrhs = 13
+    x = synth.gaussian_spinors(L, nrhs, 6)
+    f = [j % 2 for j in range(nrhs)]
+    refs = [api.dslash(api.Lattice(L, bc, MW, U, q[f[j]] * eta[f[j]]), x[j], 1) for j in range(nrhs)]
+    orders = [0] + ([1] if L[2] % 8 == 0 else []) + ([3] if L[3] % 8 == 0 else [])
+    for recon in (True, False):
+        ctx.set_link_reconstruct(recon)
+        for prec, tol in (("fp64", 1e-14), ("fp32", 2e-6), ("bf16", 2e-2)):
+            for order in orders:
+                ctx.set_launch_config(prec, "dslash", rhs_per_thread=nr, rhs_split=split, wshare=wshare,
+                                      site_order=order, blocks_per_cu=2 if order else 0)
+                assert ctx.get_launch_config(prec, "dslash")["wshare"] == wshare
+                y = _np(ctx.dslash(_t(x), f, prec=prec))
+                for j in range(nrhs):
+                    assert _rel(y[j], refs[j]) < tol, (recon, prec, order, j)
+
+
+def test_link_sharing_sign_apply():
+    """The fused Clenshaw epilogue through the link-sharing kernel, both kinds shared."""
+    L, bc = (4, 4, 8, 8), (2, 0, 0, 2)
+    U = synth.su3_links(L, 0.3, 8)
+    ctx = _ov().Context(L, bc, MW)
+    ctx.upload_gauge(_t(U))
+    ctx.set_fields((2 / 3,), (0.1,))
+    n = 40
+    eps = 0.5 / n ** 2
+    ctx.set_sign_params(n, eps, 6.5)
+    Vs = synth.random_orthonormal(L, 6, 9)
+    lam = np.linspace(-1, 1, 6)
+    ctx.upload_eigvecs(0, _t(Vs), lam)
+    x = synth.gaussian_spinors(L, 9, 5)
+    sp = api.SignParams(n, eps, 6.5, Vs, lam)
+    lat = api.Lattice(L, bc, MW, U, 2 / 3 * 0.1)
+    ref = [api.sign(lat, sp, x[j]) for j in (0, 4, 8)]
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5)):
+        for kind, cfg in (("dslash", dict(rhs_per_thread=1, rhs_split=2, wshare=4, site_order=1)),
+                          ("clenshaw", dict(rhs_per_thread=2, rhs_split=1, wshare=2, site_order=3))):
+            ctx.set_launch_config(prec, kind, **cfg)
+        for _ in range(3):   # eager, captured, replayed
+            y = _np(ctx.sign_apply(_t(x), [0] * 9, prec=prec))
+            for r, j in zip(ref, (0, 4, 8)):
+                assert _rel(y[j], r) < tol, (prec, j)
+
+
+def test_link_sharing_invalid_shapes():
+    ov = _ov()
+    ctx = ov.Context((4, 4, 4, 4), (0, 0, 0, 1), MW)
+    for cfg in (dict(wshare=3), dict(wshare=16), dict(wshare=2, rhs_per_thread=4), dict(wshare=4, rhs_split=8)):
+        with pytest.raises(ov.OvError) as e:
+            ctx.set_launch_config("fp32", "dslash", **cfg)
+        assert e.value.code == ov.OV_EINVAL
+    ctx.set_launch_config("fp32", "dslash", wshare=2)
+    ctx.set_tuning("fp32", 1, 128)
+    assert ctx.get_launch_config("fp32", "dslash")["wshare"] == 1
