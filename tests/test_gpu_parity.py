@@ -199,7 +199,7 @@ def test_stream_hint_and_per_kind_shapes(order, block, nr, split):
                               blocks_per_cu=2, stream_hint=1, rhs_split=4 if order != 1 else 1)
         got = ctx.get_launch_config(prec, "dslash")
         assert got == dict(rhs_per_thread=nr, block=block, site_order=order, blocks_per_cu=0, stream_hint=1,
-                           rhs_split=split, cols=1)
+                           rhs_split=split, cols=1, wshare=1)
         y = _np(ctx.dslash(_t(x), f, prec=prec))
         for j in (0, 1, 8):
             lat = api.Lattice(L, bc, MW, U, (2 / 3 * 1e-3, -1 / 3 * 0.2)[f[j]])
