@@ -492,8 +492,17 @@ __global__ __launch_bounds__(512) void k_dslash_lds(DsArgs<S> a)
             else { c = s / g.Lxyz; L = g.Lt; stride = g.Lxyz; }
             src = (c == 0) ? s + (L - 1) * stride : s - stride;
         }
+        // the same 16-byte pair loads as the other kernels (full cache lines over a
+        // run of consecutive sites)
+        const S *ub = a.U + (size_t)(mu * 9) * (unsigned)g.Vp;
 #pragma unroll
-        for (int k = 0; k < E; ++k) dst[k * SL] = ldc<R>(a.U, lpos<S>(mu, k, src, g.Vp));
+        for (int p = 0; p < E / 2; ++p) {   // components 0..5 (two rows) or 0..7
+            cx<R> c0, c1;
+            ldpair<S, R>(ub, g.Vp, p, (unsigned)src, c0, c1);
+            dst[(2 * p) * SL] = c0;
+            dst[(2 * p + 1) * SL] = c1;
+        }
+        if constexpr (E == 9) dst[8 * SL] = ldp<S, R>(ub + (size_t)8 * (unsigned)g.Vp, (unsigned)src);
     }
     __syncthreads();
 
