@@ -378,19 +378,16 @@ __device__ __forceinline__ int dslash_site(const Geo &g, int order, int xcd_rema
     return site_in_block(g, order, xcd_remap, cols, tb, spb);
 }
 
-// Q > 1: the Q sub-waves load the same link addresses in one instruction, so
-// a link line is fetched once for Q NR right-hand sides while every lane keeps
-// the registers of NR.
-template <class S, int NR, int Q, bool HW, bool EPI, bool REC>
-__global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
+// Work of one thread after its site and first right-hand side are known:
+// padding sites write zeros; other sites gather the 8 hops for NR RHS
+// (links from `lf`) and write the output with the optional epilogue.
+// Q == 1 means j0 is uniform over the wave, which lets the RHS offsets live
+// in scalar registers.
+template <class S, int NR, int Q, bool HW, bool EPI, class LF>
+__device__ __forceinline__ void dslash_body(const DsArgs<S> &a, int site, int j0, const LF &lf)
 {
     using R = typename StoreT<S>::real;
     const Geo &g = a.g;
-    const int site = dslash_site<Q>(g, a.order, a.xcd_remap, a.cols);
-    if (site >= g.Vp) return;
-    const int sub = (int)(threadIdx.x & 63) / (64 / Q);
-    const int j0 = (blockIdx.y * Q + sub) * NR;
-
     size_t off[NR];
     bool act[NR];
     int grp[NR];
@@ -400,7 +397,7 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
         act[r] = j < a.n;
         const int jj = act[r] ? j : 0;
         int s = a.slots ? a.slots[jj] : jj;
-        if (Q == 1) s = __builtin_amdgcn_readfirstlane(s);   // uniform: depends on blockIdx.y only
+        if (Q == 1) s = __builtin_amdgcn_readfirstlane(s);   // uniform over the wave
         off[r] = (size_t)s * (size_t)a.fstride;
         int gr = a.fgroup ? a.fgroup[s] : 0;
         if (Q == 1) gr = __builtin_amdgcn_readfirstlane(gr);
@@ -438,7 +435,6 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
 #pragma unroll
             for (int c = 0; c < 3; ++c) acc[r][sp][c] = cmk((R)0, (R)0);
 
-    const GlobalLinks<S, R, REC> lf{a.U, g.Vp};
     hop_dir<0, NR, S, R>(a, lf, site, xc, g.Lx, 1, off, act, ph, acc);
     hop_dir<1, NR, S, R>(a, lf, site, yc, g.Ly, g.Lx, off, act, ph, acc);
     hop_dir<2, NR, S, R>(a, lf, site, zc, g.Lz, g.Lxy, off, act, ph, acc);
@@ -451,6 +447,20 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
         load_spinor<S, R>(a.x + off[r], g.Vp, (unsigned)site, p);
         write_site<S, R, HW, EPI>(a, off[r], (unsigned)site, p, acc[r]);
     }
+}
+
+// Q > 1: the Q sub-waves load the same link addresses in one instruction, so
+// a link line is fetched once for Q NR right-hand sides while every lane keeps
+// the registers of NR.
+template <class S, int NR, int Q, bool HW, bool EPI, bool REC>
+__global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
+{
+    using R = typename StoreT<S>::real;
+    const int site = dslash_site<Q>(a.g, a.order, a.xcd_remap, a.cols);
+    if (site >= a.g.Vp) return;
+    const int sub = (int)(threadIdx.x & 63) / (64 / Q);
+    const GlobalLinks<S, R, REC> lf{a.U, a.g.Vp};
+    dslash_body<S, NR, Q, HW, EPI>(a, site, (blockIdx.y * Q + sub) * NR, lf);
 }
 
 // ---------------------------------------------------------------------------
@@ -512,66 +522,8 @@ __global__ __launch_bounds__(512) void k_dslash_lds(DsArgs<S> a)
     const int sub = lane / SL;
     const int j0 = ((blockIdx.y * W + wave) * Q + sub) * NR;
 
-    size_t off[NR];
-    bool act[NR];
-    int grp[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int j = j0 + r;
-        act[r] = j < a.n;
-        const int jj = act[r] ? j : 0;
-        int s = a.slots ? a.slots[jj] : jj;
-        if (Q == 1) s = __builtin_amdgcn_readfirstlane(s);   // uniform: depends on blockIdx.y and the wave
-        off[r] = (size_t)s * (size_t)a.fstride;
-        int gr = a.fgroup ? a.fgroup[s] : 0;
-        if (Q == 1) gr = __builtin_amdgcn_readfirstlane(gr);
-        grp[r] = gr;
-    }
-    if (site >= g.V) {   // padding sites hold zeros in every field
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            if (!act[r]) continue;
-#pragma unroll
-            for (int q = 0; q < 6; ++q)
-                stpair<S, R>(a.y + off[r], g.Vp, q, (unsigned)site, cmk((R)0, (R)0), cmk((R)0, (R)0));
-        }
-        return;
-    }
-
-    int rem = site;
-    const int xc = rem % g.Lx; rem /= g.Lx;
-    const int yc = rem % g.Ly; rem /= g.Ly;
-    const int zc = rem % g.Lz;
-    const int tc = rem / g.Lz;
-
-    cx<R> ph[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const cx<double> p = a.phase[grp[r] * g.Lt + tc];
-        ph[r] = cmk((R)p.x, (R)p.y);
-    }
-
-    cx<R> acc[NR][4][3];
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) acc[r][sp][c] = cmk((R)0, (R)0);
-
     const LdsLinks<R, REC, SL> lf{lk, sl};
-    hop_dir<0, NR, S, R>(a, lf, site, xc, g.Lx, 1, off, act, ph, acc);
-    hop_dir<1, NR, S, R>(a, lf, site, yc, g.Ly, g.Lx, off, act, ph, acc);
-    hop_dir<2, NR, S, R>(a, lf, site, zc, g.Lz, g.Lxy, off, act, ph, acc);
-    hop_dir<3, NR, S, R>(a, lf, site, tc, g.Lt, g.Lxyz, off, act, ph, acc);
-
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        if (!act[r]) continue;
-        cx<R> p[4][3];
-        load_spinor<S, R>(a.x + off[r], g.Vp, (unsigned)site, p);
-        write_site<S, R, HW, EPI>(a, off[r], (unsigned)site, p, acc[r]);
-    }
+    dslash_body<S, NR, Q, HW, EPI>(a, site, j0, lf);
 }
 
 // ---------------------------------------------------------------------------
