@@ -174,6 +174,43 @@ int ov_sign_apply(ov_ctx *ctx, int prec, int nrhs, const int *field_of_rhs,
                   const void *x_dev, void *y_dev);
 
 /*
+ * Norm safety of the polynomial sign (Sec. 2: Q = H_w / ||H_w|| must have
+ * its spectrum in [-1, 1], where the Chebyshev recursion is bounded).
+ *
+ * Every sign application compares, per RHS, w = Q P(Q^2) chi with the bound
+ * ||w|| <= 1.02 M ||chi||, M = max_{|q| <= 1} |q P(q^2)| of the current
+ * coefficients (M is within 1e-5 of 1 for the built-in interpolant).  The
+ * bound holds whenever the norm passed to ov_set_sign_params is at least
+ * ||H_w|| of the applied links; when it is too small the recursion grows
+ * like T_n outside [-1, 1] (at degree 300 a spectrum 1 % beyond the bound
+ * amplifies components by ~1e25) and the comparison fails.  A failure sets
+ * a sticky flag on the device; the result of that application is then not
+ * the polynomial sign.
+ *   mode 0: no check;
+ *   mode 1: the flag is reported as OV_ENORM by the synchronising entry
+ *           points that apply the sign (deflated CG, multi-mass CG, D_ov
+ *           eigensolver, sign adjoint, correlator derivative), which clear it
+ *           on entry, and by ov_norm_status;
+ *   mode 2 (default): as 1, and ov_sign_apply / ov_dov_apply synchronise
+ *           and return OV_ENORM themselves.
+ * After OV_ENORM the context stays usable: set a larger norm and repeat.
+ * ov_norm_status synchronises, returns OV_ENORM if the flag is set (and
+ * clears it), OV_OK otherwise.
+ *
+ * The FP32 and BF16 kernels apply links rounded to their storage (two-row
+ * links: with the rebuilt third row), whose H_w norm may exceed that of the
+ * uploaded links by 4 max_x ||U_eff(x) - U(x)||_2 (four directions, one
+ * link norm each).  ov_upload_gauge measures that distance (Frobenius norm,
+ * an upper bound of the spectral one) and the sign pipeline of those
+ * precisions divides by norm + 4 (distance + 1e-6) (the 1e-6 covers the
+ * FP32 evaluation of the rebuilt row).  ov_get_sign_norm returns the norm
+ * used for precision prec.
+ */
+int ov_set_norm_check(ov_ctx *ctx, int mode);
+int ov_norm_status(ov_ctx *ctx);
+int ov_get_sign_norm(ov_ctx *ctx, int prec, double *norm);
+
+/*
  * y = D(m) x with D(m) = (1 - m/2) D_ov + m, D_ov = 1 + gamma5 s (Sec. 2,
  * eq. (1); m = 0 is eq. (1) itself), or y = D(m)^dag x = gamma5 D(m) gamma5 x
  * when dagger != 0.  mass: host array of nrhs quark masses.
@@ -332,6 +369,27 @@ int ov_dov_eigensolve(ov_ctx *ctx, int field, int chirality, const ov_eig_opts *
  * reduction.  out: host [nrhs][Lt].  Synchronises.
  */
 int ov_timeslice_norm2(ov_ctx *ctx, int nrhs, const void *x_dev, double *out);
+
+/*
+ * Connected pseudoscalar (pion) correlator of one flavour (Sec. 4, eq. (4):
+ * two-point functions from which R(t) is formed): with gamma5-hermiticity,
+ *   G[t] = sum_j sum over the sites of time slice t and the 12 spin-colour
+ *          components of |S_j|^2,
+ * for the nsrc point-source propagators S_dev [nsrc][V][4][3] complex128
+ * (normally the 12 spin-colour sources of one operator).  The per-slice sums
+ * and the sum over j run on the device in a fixed order (deterministic).
+ * G: host [Lt].  Synchronises.
+ */
+int ov_pion_correlator(ov_ctx *ctx, int nsrc, const void *S_dev, double *G);
+
+/*
+ * R(t) = G_E(t) / G_0(t) (Sec. 4): G_E is the mean of the nE field
+ * correlators G_E_all [nE][Lt] (u and d quarks at +E and -E: nE = 4) and G_0
+ * the correlator without field [Lt].  Host utility, no context, no GPU.
+ * R: host [Lt].  OV_EINVAL for Lt < 1, nE < 1, a null pointer or a G_0[t]
+ * that is not a positive finite number; OV_ENAN for a non-finite G_E sum.
+ */
+int ov_ratio_R(int Lt, int nE, const double *G_E_all, const double *G_0, double *R);
 
 /*
  * Derivative of a correlator with respect to the background field (Sec. 4:

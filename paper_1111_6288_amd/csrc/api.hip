@@ -80,6 +80,14 @@ struct ov_ctx {
     double eps = 0, norm = 0;
     std::vector<double> coef;
 
+    // norm safety: max Frobenius |U_eff - U| of the links the FP32 / BF16
+    // kernels apply ([prec][0 nine entries, 1 two rows + rebuilt third]),
+    // the growth bound of the current polynomial and the check mode
+    double link_dev[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    std::vector<double> bound_coef;   // coefficients sign_bound2 was computed for
+    double sign_bound2 = 0;
+    int norm_check = 2;               // 0 off; 1 flag only; 2 flag and sign/D(m) applies synchronise
+
     std::vector<Small> small;
     std::vector<Defl> defl;
 
@@ -105,8 +113,14 @@ struct ov_ctx {
     size_t ev_used = 0;
     std::vector<ProfRec> recs;
 
-    // persistent small device scratch
+    // persistent small device scratch: [0] non-finite count, [8] row-3 deviation bits,
+    // [16] norm-breach flag, [32..63] link rounding deviation bits
     int *d_count = nullptr;
+
+    // pinned host words for the lagged reads of the CG's active flags
+    int *h_pin = nullptr;
+    size_t h_pin_n = 0;
+    hipEvent_t ev_mask[2] = {nullptr, nullptr};
 
     size_t mem_bytes = 0;
 
@@ -521,11 +535,92 @@ int proj_expand(ov_ctx *c, const double2 *V, int l, const SX *X, double alpha, S
     return OV_OK;
 }
 
+// ---------------------------------------------------------------- norm safety
+int *norm_flag(const ov_ctx *c) { return (int *)((char *)c->d_count + 16); }
+
+// Norm that the kernels of precision S divide H_w by.  The FP32 and BF16
+// kernels apply rounded links U_eff with ||H_w(U_eff)|| <= ||H_w(U)|| +
+// 4 max ||U_eff - U||: the hopping term of one direction has norm max ||U||
+// (its two halves act on complementary spin projectors), and there are four
+// directions.  A bound for the uploaded links therefore becomes one for the
+// applied links after adding that margin (plus 1e-6 per link for the FP32
+// evaluation of a rebuilt third row).
+template <class S>
+double norm_of(const ov_ctx *c)
+{
+    const int p = PrecOf<S>::p;
+    if (p == OV_FP64) return c->norm;
+    return c->norm + 4.0 * (c->link_dev[p][c->recon ? 1 : 0] + 1e-6);
+}
+
+// (slack * max_{0 <= q <= 1} |q P(q^2)|)^2 for the current coefficients, on a
+// grid of q (P evaluated by Clenshaw in FP64).  The interpolant of y^{-1/2}
+// gives a maximum within 1e-5 of 1; the 2 % slack covers the grid and the
+// rounding of an FP32 recursion.  Outside [-1, 1] the polynomial grows like
+// a Chebyshev polynomial (at degree 300 a spectrum 1 % beyond the bound
+// multiplies some components by ~1e25), which is what the check detects.
+void update_sign_bound(ov_ctx *c)
+{
+    if (c->bound_coef == c->coef) return;
+    const int n = (int)c->coef.size() - 1;
+    const int G = n <= 2000 ? 4001 : 1001;
+    double M = 0.0;
+    for (int i = 0; i <= G; ++i) {
+        const double q = (double)i / G;
+        const double x = (2.0 * q * q - 1.0 - c->eps) / (1.0 - c->eps);
+        double b1 = 0.0, b2 = 0.0;
+        for (int k = n; k >= 1; --k) {
+            const double b0 = c->coef[k] + 2.0 * x * b1 - b2;
+            b2 = b1;
+            b1 = b0;
+        }
+        const double v = q * (c->coef[0] + x * b1 - b2);
+        M = std::max(M, std::fabs(v));
+    }
+    const double b = 1.02 * M;
+    c->sign_bound2 = b * b;
+    c->bound_coef = c->coef;
+}
+
+// Read and clear the norm-breach flag (synchronises).  OV_ENORM if a sign
+// application since the last clear saw the polynomial grow beyond its bound.
+int take_norm_flag(ov_ctx *c)
+{
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, norm_flag(c), sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (!h) return OV_OK;
+    HIPCHK(launch_fill_int(norm_flag(c), 1, 0, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return fail(c, OV_ENORM,
+                "norm bound %.6g is below ||H_w||: the Chebyshev recursion grew beyond its bound on [-1, 1] "
+                "(pass a larger norm to ov_set_sign_params)",
+                c->norm);
+}
+
+// Clear the flag at the start of a synchronising entry point.
+int clear_norm_flag(ov_ctx *c)
+{
+    HIPCHK(launch_fill_int(norm_flag(c), 1, 0, c->stream));
+    return OV_OK;
+}
+
+// Result of a synchronising entry point: a breach seen during the call takes
+// precedence over OV_ENOCONV / OV_ENAN (both are what a breach produces).
+int with_norm_status(ov_ctx *c, int rc)
+{
+    if (c->norm_check == 0 || !(rc == OV_OK || rc == OV_ENOCONV || rc == OV_ENAN || rc == OV_EBREAKDOWN))
+        return rc;
+    const int r2 = take_norm_flag(c);
+    return r2 != OV_OK ? r2 : rc;
+}
+
 // ---------------------------------------------------------------- sign pipeline
 template <class S>
 struct SignBufs {
     S *chi = nullptr, *B[3] = {nullptr, nullptr, nullptr}, *T = nullptr;
     double2 *C = nullptr, *D = nullptr, *E = nullptr, *part = nullptr;
+    double2 *npart = nullptr, *chi2 = nullptr, *w2 = nullptr;   // norm check: dot partials, |chi|^2, |w|^2
 };
 
 size_t small_arrays_bytes(const ov_ctx *c, int nstore)
@@ -535,7 +630,8 @@ size_t small_arrays_bytes(const ov_ctx *c, int nstore)
     for (auto &d : c->defl) lmax = std::max(lmax, d.k);
     const long K = 12L * c->g.Vp;
     const long nchunk = (K + proj_dot_chunk(K) - 1) / proj_dot_chunk(K);
-    return 3 * align_up((size_t)nstore * lmax * 16) + align_up((size_t)nchunk * 48 * 256 * 16);
+    return 3 * align_up((size_t)nstore * lmax * 16) + align_up((size_t)nchunk * 48 * 256 * 16) +
+           align_up((8192 + (size_t)nstore) * 16) + 2 * align_up((size_t)nstore * 16);
 }
 
 template <class S>
@@ -554,7 +650,10 @@ int take_sign_bufs(ov_ctx *c, int nstore, SignBufs<S> &w)
     const long K = 12L * c->g.Vp;
     const long nchunk = (K + proj_dot_chunk(K) - 1) / proj_dot_chunk(K);
     w.part = ws_take<double2>(c, (size_t)nchunk * 48 * 256);
-    if (!w.chi || !w.B[2] || !w.T || !w.part) return fail(c, OV_ENOMEM, "workspace too small (internal)");
+    w.npart = ws_take<double2>(c, 8192 + (size_t)nstore);
+    w.chi2 = ws_take<double2>(c, nstore);
+    w.w2 = ws_take<double2>(c, nstore);
+    if (!w.chi || !w.B[2] || !w.T || !w.part || !w.w2) return fail(c, OV_ENOMEM, "workspace too small (internal)");
     return OV_OK;
 }
 
@@ -602,8 +701,17 @@ int sign_batch(ov_ctx *c, const Batch &b, const int *fgroup, const S *X, S *OUT,
         }
     }
 
+    // |chi|^2 per RHS for the norm check (before OUT, which may alias X = chi, is written)
+    const bool check = c->norm_check != 0;
+    const long fe = (long)field_elems(c);
+    if (check) {
+        update_sign_bound(c);
+        HIPCHK((launch_dot<S, S>(chi, fe, chi, fe, b.slots, b.n, c->g.Vp, 0, w.npart, w.chi2, b.slots, c->stream)));
+    }
+
     // 2. Clenshaw recursion
-    const double al = 2.0 / ((1.0 - c->eps) * c->norm * c->norm);
+    const double N = norm_of<S>(c);
+    const double al = 2.0 / ((1.0 - c->eps) * N * N);
     const double be = (1.0 + c->eps) / (1.0 - c->eps);
     const int n = c->npoly;
     {
@@ -627,7 +735,11 @@ int sign_batch(ov_ctx *c, const Batch &b, const int *fgroup, const S *X, S *OUT,
 
     // 3. w = Q z
     S *wout = any_small ? w.T : OUT;
-    CHK(dslash_launch<S>(c, b, fgroup, w.B[iz], wout, 1.0 / c->norm, true));
+    CHK(dslash_launch<S>(c, b, fgroup, w.B[iz], wout, 1.0 / N, true));
+    if (check) {   // ||w|| <= M ||chi|| holds whenever the spectrum of Q lies in [-1, 1]
+        HIPCHK((launch_dot<S, S>(wout, fe, wout, fe, b.slots, b.n, c->g.Vp, 0, w.npart, w.w2, b.slots, c->stream)));
+        HIPCHK(launch_norm_breach(w.chi2, w.w2, b.slots, b.n, c->sign_bound2, norm_flag(c), c->stream));
+    }
 
     // 4. OUT = w - V (V^dag w) + V sgn C
     if (any_small) {
@@ -825,7 +937,7 @@ int api_sign(ov_ctx *c, int nrhs, const std::vector<int> &grp, const void *x, vo
     CHK(run_graph(c, key, [&]() { return sign_batch<S>(c, b, fg, X, X, w); }));
     HIPCHK(launch_unpack_spinor<S>(X, (double2 *)y, (long)field_elems(c), nullptr, nrhs, c->g.V, c->g.Vp,
                                    c->stream));
-    return OV_OK;
+    return c->norm_check == 2 ? take_norm_flag(c) : OV_OK;
 }
 
 template <class S>
@@ -849,7 +961,7 @@ int api_dov(ov_ctx *c, int nrhs, const std::vector<int> &grp, const double *mass
     CHK(run_graph(c, key, [&]() { return dov_batch<S>(c, b, fg, ca, cb, dagger != 0, X, X, w); }));
     HIPCHK(launch_unpack_spinor<S>(X, (double2 *)y, (long)field_elems(c), nullptr, nrhs, c->g.V, c->g.Vp,
                                    c->stream));
-    return OV_OK;
+    return c->norm_check == 2 ? take_norm_flag(c) : OV_OK;
 }
 
 }  // namespace
@@ -893,6 +1005,11 @@ int ov_create(const int32_t L[4], const int32_t bc[4], double m_w, int device, o
         delete c;
         return OV_ENOMEM;
     }
+    if (hipMemset(c->d_count, 0, 256) != hipSuccess) {
+        (void)hipFree(c->d_count);
+        delete c;
+        return OV_EHIP;
+    }
     *out = c;
     return OV_OK;
 }
@@ -917,6 +1034,9 @@ int ov_destroy(ov_ctx *c)
     for (auto &kv : c->dcache) (void)hipFree(kv.second);
     for (auto &kv : c->ccache) (void)hipFree(kv.second);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    for (auto e : c->ev_mask)
+        if (e) (void)hipEventDestroy(e);
+    if (c->h_pin) (void)hipHostFree(c->h_pin);
     invalidate_graphs(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
@@ -961,8 +1081,16 @@ int ov_upload_gauge(ov_ctx *c, const void *U_dev)
     HIPCHK(hipMemsetAsync(d_dev, 0, sizeof(dev_bits), c->stream));
     HIPCHK(launch_link_row3_dev((const double2 *)U_dev, 4L * c->g.V, d_dev, c->stream));
     HIPCHK(hipMemcpyAsync(&dev_bits, d_dev, sizeof(dev_bits), hipMemcpyDeviceToHost, c->stream));
+    unsigned long long *rd_dev = (unsigned long long *)((char *)c->d_count + 32);
+    unsigned long long rd_bits[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemsetAsync(rd_dev, 0, sizeof(rd_bits), c->stream));
+    HIPCHK(launch_link_round_dev((const double2 *)U_dev, 4L * c->g.V, rd_dev, c->stream));
+    HIPCHK(hipMemcpyAsync(rd_bits, rd_dev, sizeof(rd_bits), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     std::memcpy(&c->row3_dev, &dev_bits, sizeof(double));
+    for (int p = 0; p < 2; ++p)
+        for (int r = 0; r < 2; ++r) std::memcpy(&c->link_dev[1 + p][r], &rd_bits[2 * p + r], sizeof(double));
+    invalidate_graphs(c);   // the FP32 / BF16 norms baked into captured pipelines may change
     c->have_gauge = true;
     update_link_format(c);
     return OV_OK;
@@ -1108,6 +1236,32 @@ int ov_dslash(ov_ctx *c, int prec, int op, int nrhs, const int *field_of_rhs, co
     if (prec == OV_FP64) return api_dslash<double2>(c, op, nrhs, grp, x, y);
     if (prec == OV_FP32) return api_dslash<float2>(c, op, nrhs, grp, x, y);
     return api_dslash<uint32_t>(c, op, nrhs, grp, x, y);
+}
+
+int ov_set_norm_check(ov_ctx *c, int mode)
+{
+    CHK(check_ctx(c));
+    if (mode < 0 || mode > 2) return fail(c, OV_EINVAL, "norm check mode must be 0, 1 or 2");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if ((mode == 0) != (c->norm_check == 0)) invalidate_graphs(c);   // captures hold the check kernels
+    c->norm_check = mode;
+    return OV_OK;
+}
+
+int ov_norm_status(ov_ctx *c)
+{
+    CHK(check_ctx(c));
+    return take_norm_flag(c);
+}
+
+int ov_get_sign_norm(ov_ctx *c, int prec, double *norm)
+{
+    CHK(check_ctx(c));
+    CHK(check_prec(c, prec));
+    if (!norm) return fail(c, OV_EINVAL, "null argument");
+    if (!c->have_sign) return fail(c, OV_ESTATE, "sign parameters not set");
+    *norm = prec == OV_FP64 ? norm_of<double2>(c) : prec == OV_FP32 ? norm_of<float2>(c) : norm_of<uint32_t>(c);
+    return OV_OK;
 }
 
 int ov_sign_apply(ov_ctx *c, int prec, int nrhs, const int *field_of_rhs, const void *x, void *y)
@@ -1292,9 +1446,60 @@ namespace {
 struct CgScalars {
     double *rr, *rr_new, *stop, *red;
     double2 *pAp, *ap, *an, *beta, *one;
-    int *active;
+    int *active, *iters;
     double2 *dpart;
 };
+
+// Pinned host words for reading the active flags while the next iteration runs.
+int pin_reserve(ov_ctx *c, size_t n)
+{
+    for (auto &e : c->ev_mask)
+        if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (n <= c->h_pin_n) return OV_OK;
+    if (c->h_pin) HIPCHK(hipHostFree(c->h_pin));
+    c->h_pin = nullptr;
+    c->h_pin_n = 0;
+    HIPCHK(hipHostMalloc((void **)&c->h_pin, n * sizeof(int), hipHostMallocDefault));
+    c->h_pin_n = n;
+    return OV_OK;
+}
+
+void key_ptrs(std::string &k, std::initializer_list<const void *> ps)
+{
+    for (const void *p : ps) k.append((const char *)&p, sizeof p);
+    k.push_back('|');
+}
+
+// One inner CG iteration on batch bi: Ap = D^dag D p, alpha, e += alpha p,
+// r -= alpha Ap (with |r|^2), beta and the active flags on the device,
+// p = r + beta p.  Kernel launches only (captured as one graph per batch).
+template <class S>
+int cg_iteration(ov_ctx *c, const Batch &bi, const int *fg, const double2 *ca, const double2 *cb, S *E, S *r, S *p,
+                 S *Ap, S *Dp, DovBufs<S> &w, CgScalars &s, int nstore)
+{
+    const long fe = (long)field_elems(c);
+    int nb = 0;
+    CHK(dov_batch<S>(c, bi, fg, ca, cb, false, p, Dp, w));
+    CHK(dov_batch<S>(c, bi, fg, ca, cb, true, Dp, Ap, w));
+    HIPCHK((launch_dot<S, S>(p, fe, Ap, fe, bi.slots, bi.n, c->g.Vp, 0, s.dpart, s.pAp, bi.slots, c->stream)));
+    HIPCHK(launch_cg_alpha(s.rr, s.pAp, s.active, nstore, s.ap, s.an, c->stream));
+    {   // e += alpha p ; r -= alpha Ap (with |r|^2)
+        const S *in1[2] = {E, p};
+        const double2 *cf1[2] = {s.one, s.ap};
+        CHK((lincomb<S, S>(c, bi, E, 2, in1, cf1, nullptr, 0)));
+        const S *in2[2] = {r, Ap};
+        const double2 *cf2[2] = {s.one, s.an};
+        CHK((lincomb<S, S>(c, bi, r, 2, in2, cf2, nullptr, 0, s.red, &nb)));
+        HIPCHK(launch_reduce_r(s.red, nb, bi.n, s.rr_new, bi.slots, c->stream));
+    }
+    HIPCHK(launch_cg_beta(s.rr_new, s.rr, s.active, s.stop, nstore, s.beta, s.iters, c->stream));
+    {   // p = r + beta p
+        const S *in[2] = {r, p};
+        const double2 *cf[2] = {s.one, s.beta};
+        CHK((lincomb<S, S>(c, bi, p, 2, in, cf, nullptr, 0)));
+    }
+    return OV_OK;
+}
 
 template <class S>
 size_t cg_inner_bytes(const ov_ctx *c, int n)
@@ -1395,41 +1600,45 @@ int inner_cg(ov_ctx *c, const Batch &bo, const std::vector<int> &grp, const int 
     HIPCHK(h2d(c, s.stop, stop.data(), 8ul * nstore));
     HIPCHK(h2d(c, s.active, act.data(), 4ul * nstore));
 
+    HIPCHK(launch_fill_int(s.iters, nstore, 0, c->stream));
+    CHK(pin_reserve(c, 2ul * nstore));
+    int *hb[2] = {c->h_pin, c->h_pin + nstore};
+
+    // The convergence test runs on the device (k_cg_beta clears a RHS's
+    // active flag and stops counting its iterations); the host reads the
+    // flags of iteration i while iteration i + 1 is already queued and drops
+    // converged RHS from the batch of iteration i + 2.  A converged RHS that
+    // rides along for one more iteration has alpha = 0: its e and r stay
+    // unchanged.  Each batch's iteration is captured as one graph.
     std::vector<int> cur;
     for (int j : bo.slots_h)
         if (act[j]) cur.push_back(j);
+    const std::string kbase = "cgit|" + std::to_string(PrecOf<S>::p) + "|";
+    int pending = -1;
     while (!cur.empty() && total < budget) {
         Batch bi;
         CHK(make_batch(c, cur, grp, bi));
-        // Ap = D^dag D p
-        CHK(dov_batch<S>(c, bi, fg, ca, cb, false, p, Dp, w));
-        CHK(dov_batch<S>(c, bi, fg, ca, cb, true, Dp, Ap, w));
-        HIPCHK((launch_dot<S, S>(p, fe, Ap, fe, bi.slots, bi.n, c->g.Vp, 0, s.dpart, s.pAp, bi.slots, c->stream)));
-        HIPCHK(launch_cg_alpha(s.rr, s.pAp, s.active, nstore, s.ap, s.an, c->stream));
-        {   // e += alpha p ; r -= alpha Ap (with |r|^2)
-            const S *in1[2] = {E, p};
-            const double2 *cf1[2] = {s.one, s.ap};
-            CHK((lincomb<S, S>(c, bi, E, 2, in1, cf1, nullptr, 0)));
-            const S *in2[2] = {r, Ap};
-            const double2 *cf2[2] = {s.one, s.an};
-            CHK((lincomb<S, S>(c, bi, r, 2, in2, cf2, nullptr, 0, s.red, &nb)));
-            HIPCHK(launch_reduce_r(s.red, nb, bi.n, s.rr_new, bi.slots, c->stream));
-        }
-        HIPCHK(launch_cg_beta(s.rr_new, s.rr, s.active, s.stop, nstore, s.beta, c->stream));
-        {   // p = r + beta p
-            const S *in[2] = {r, p};
-            const double2 *cf[2] = {s.one, s.beta};
-            CHK((lincomb<S, S>(c, bi, p, 2, in, cf, nullptr, 0)));
-        }
-        for (int j : cur) iters[j] += 1;
+        std::string key = kbase;
+        key_ptrs(key, {E, r, p, Ap, Dp, s.rr, s.active, s.iters, ca, cb, fg, w.XG, w.sb.chi});
+        key_add(key, cur);
+        CHK(run_graph(c, key, [&]() { return cg_iteration<S>(c, bi, fg, ca, cb, E, r, p, Ap, Dp, w, s, nstore); }));
         total += 1;
-        HIPCHK(hipMemcpyAsync(act.data(), s.active, 4ul * nstore, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        std::vector<int> nxt;
-        for (int j : cur)
-            if (act[j]) nxt.push_back(j);
-        cur.swap(nxt);
+        const int slot = total & 1;
+        HIPCHK(hipMemcpyAsync(hb[slot], s.active, 4ul * nstore, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipEventRecord(c->ev_mask[slot], c->stream));
+        if (pending >= 0) {
+            HIPCHK(hipEventSynchronize(c->ev_mask[pending]));
+            std::vector<int> nxt;
+            for (int j : cur)
+                if (hb[pending][j]) nxt.push_back(j);
+            cur.swap(nxt);
+        }
+        pending = slot;
     }
+    std::vector<int> hit(nstore, 0);
+    HIPCHK(hipMemcpyAsync(hit.data(), s.iters, 4ul * nstore, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int j : bo.slots_h) iters[j] += hit[j];
     return OV_OK;
 }
 
@@ -1440,7 +1649,7 @@ int api_cg(ov_ctx *c, int nrhs, const std::vector<int> &grp, const double *mass,
     const int n = nrhs;
     const size_t f64 = align_up(field_bytes<double2>(c) * n);
     const size_t regionA = std::max(dov_bufs_bytes<double2>(c, n) + f64, cg_inner_bytes<S>(c, n));
-    const size_t scal = 16 * align_up(16ul * n) + 2 * align_up(16ul * (8192 + n));
+    const size_t scal = 17 * align_up(16ul * n) + 2 * align_up(16ul * (8192 + n));
     CHK(ws_reserve(c, 4 * f64 + regionA + scal));
     double2 *B64 = ws_take<double2>(c, field_elems(c) * n);
     double2 *X64 = ws_take<double2>(c, field_elems(c) * n);
@@ -1456,6 +1665,7 @@ int api_cg(ov_ctx *c, int nrhs, const std::vector<int> &grp, const double *mass,
     s.beta = ws_take<double2>(c, n);
     s.one = ws_take<double2>(c, n);
     s.active = ws_take<int>(c, n);
+    s.iters = ws_take<int>(c, n);
     // partial sums: a launch over n RHS uses at most max(8192, n) blocks in total
     s.red = ws_take<double>(c, 8192 + (size_t)n);
     s.dpart = ws_take<double2>(c, 8192 + (size_t)n);
@@ -1507,6 +1717,7 @@ int api_cg(ov_ctx *c, int nrhs, const std::vector<int> &grp, const double *mass,
     for (;;) {
         std::vector<double> res2;
         CHK(norms2(c, ball, R64, s, n, res2));
+        if (c->norm_check) CHK(take_norm_flag(c));   // norms2 synchronised: the flag is current
         std::vector<int> todo;
         for (int j = 0; j < n; ++j) {
             if (!std::isfinite(res2[j])) return fail(c, OV_ENAN, "non-finite residual for RHS %d", j);
@@ -1740,9 +1951,12 @@ int ov_deflated_cg(ov_ctx *c, int nrhs, const int *field_of_rhs, const double *m
     CHK(check_fields(c, nrhs, field_of_rhs, grp));
     for (int j = 0; j < nrhs; ++j)
         if (!std::isfinite(mass[j])) return fail(c, OV_ENAN, "non-finite mass");
-    if (opts->inner_prec == OV_FP64) return api_cg<double2>(c, nrhs, grp, mass, b_dev, x_dev, *opts, report);
-    if (opts->inner_prec == OV_FP32) return api_cg<float2>(c, nrhs, grp, mass, b_dev, x_dev, *opts, report);
-    return api_cg<uint32_t>(c, nrhs, grp, mass, b_dev, x_dev, *opts, report);
+    CHK(clear_norm_flag(c));
+    if (opts->inner_prec == OV_FP64)
+        return with_norm_status(c, api_cg<double2>(c, nrhs, grp, mass, b_dev, x_dev, *opts, report));
+    if (opts->inner_prec == OV_FP32)
+        return with_norm_status(c, api_cg<float2>(c, nrhs, grp, mass, b_dev, x_dev, *opts, report));
+    return with_norm_status(c, api_cg<uint32_t>(c, nrhs, grp, mass, b_dev, x_dev, *opts, report));
 }
 
 int ov_upload_deflation(ov_ctx *c, int field, int k, const void *W_dev)
@@ -1813,7 +2027,9 @@ int ov_sign_backward(ov_ctx *c, int field, const void *x_dev, const void *g_dev,
     if (!x_dev || !g_dev) return fail(c, OV_EINVAL, "null x or g");
     if (ckpt_every < 1) return fail(c, OV_EINVAL, "ckpt_every must be >= 1");
     if (!c->have_gauge || !c->have_sign) return fail(c, OV_ESTATE, "upload the gauge field and set the sign first");
-    return api_backward(c, field, x_dev, g_dev, gU_dev, geta, gx_dev, std::min(ckpt_every, c->npoly));
+    CHK(clear_norm_flag(c));
+    return with_norm_status(c, api_backward(c, field, x_dev, g_dev, gU_dev, geta, gx_dev,
+                                            std::min(ckpt_every, c->npoly)));
 }
 
 int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
@@ -2594,9 +2810,10 @@ int ov_multishift_cg(ov_ctx *c, int nrhs, const int *field_of_rhs, int nmass, co
     if (o->inner_prec != OV_FP64 && o->inner_prec != OV_FP32) return fail(c, OV_EINVAL, "inner_prec must be FP64 or FP32");
     std::vector<int> grp;
     CHK(check_fields(c, nrhs, field_of_rhs, grp));
+    CHK(clear_norm_flag(c));
     if (o->inner_prec == OV_FP32)
-        return api_mscg<float2>(c, nrhs, grp, nmass, mass, b_dev, x_dev, *o, report, relres);
-    return api_mscg<double2>(c, nrhs, grp, nmass, mass, b_dev, x_dev, *o, report, relres);
+        return with_norm_status(c, api_mscg<float2>(c, nrhs, grp, nmass, mass, b_dev, x_dev, *o, report, relres));
+    return with_norm_status(c, api_mscg<double2>(c, nrhs, grp, nmass, mass, b_dev, x_dev, *o, report, relres));
 }
 
 }  // extern "C"
@@ -2806,7 +3023,9 @@ int ov_dov_eigensolve(ov_ctx *c, int field, int chirality, const ov_eig_opts *o,
     if (o->max_iter < 1) return fail(c, OV_EINVAL, "max_iter must be >= 1");
     if (!(o->tol > 0)) return fail(c, OV_EINVAL, "tol must be positive");
     if (o->prec != OV_FP64 && o->prec != OV_FP32) return fail(c, OV_EINVAL, "filter precision must be FP64 or FP32");
-    const int rc = api_dov_eigensolve(c, field, chirality, *o, X0_dev, W_dev, lambda, resid, report);
+    CHK(clear_norm_flag(c));
+    const int rc = with_norm_status(c, api_dov_eigensolve(c, field, chirality, *o, X0_dev, W_dev, lambda, resid,
+                                                          report));
     if (rc != OV_OK && rc != OV_ENOCONV) return rc;
     if (install) CHK(ov_upload_deflation(c, field, o->l, W_dev));
     return rc == OV_OK ? OV_OK : fail(c, OV_ENOCONV, "D_ov eigensolver did not converge (basis installed anyway)");
@@ -2831,6 +3050,37 @@ int ov_timeslice_norm2(ov_ctx *c, int nrhs, const void *x_dev, double *out)
     HIPCHK(launch_slice_norm2((const double2 *)x_dev, nrhs, c->g.V, Lxyz, Lt, part, o, c->stream));
     HIPCHK(hipMemcpyAsync(out, o, 8 * m, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    return OV_OK;
+}
+
+int ov_pion_correlator(ov_ctx *c, int nsrc, const void *S_dev, double *G)
+{
+    CHK(check_ctx(c));
+    if (nsrc < 1 || nsrc > 65535) return fail(c, OV_EINVAL, "nsrc outside [1, 65535]");
+    if (!S_dev || !G) return fail(c, OV_EINVAL, "null argument");
+    const int Lxyz = c->g.Lxyz, Lt = c->g.Lt;
+    const int nb = slice_norm2_blocks(Lxyz);
+    const size_t m = (size_t)nsrc * Lt;
+    CHK(ws_reserve(c, align_up(8 * m * nb) + align_up(8 * m) + align_up(8ul * Lt)));
+    double *part = ws_take<double>(c, m * nb), *o = ws_take<double>(c, m), *Gd = ws_take<double>(c, Lt);
+    if (!Gd) return fail(c, OV_ENOMEM, "workspace too small (internal)");
+    HIPCHK(launch_slice_norm2((const double2 *)S_dev, nsrc, c->g.V, Lxyz, Lt, part, o, c->stream));
+    HIPCHK(launch_sum_rows(o, nsrc, Lt, Gd, c->stream));
+    HIPCHK(hipMemcpyAsync(G, Gd, 8ul * Lt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return OV_OK;
+}
+
+int ov_ratio_R(int Lt, int nE, const double *G_E, const double *G_0, double *R)
+{
+    if (Lt < 1 || nE < 1 || !G_E || !G_0 || !R) return OV_EINVAL;
+    for (int t = 0; t < Lt; ++t) {
+        if (!(G_0[t] > 0) || !std::isfinite(G_0[t])) return OV_EINVAL;
+        double s = 0.0;
+        for (int e = 0; e < nE; ++e) s += G_E[(size_t)e * Lt + t];
+        if (!std::isfinite(s)) return OV_ENAN;
+        R[t] = (s / nE) / G_0[t];
+    }
     return OV_OK;
 }
 
@@ -2869,6 +3119,7 @@ int ov_correlator_deta(ov_ctx *c, int field, double mass, int nsrc, const void *
         cleanup();
         return rc;
     }
+    CHK(clear_norm_flag(c));
     std::vector<int> grp(nsrc, field);
     std::vector<double> mv(nsrc, mass);
     std::vector<ov_cg_rhs_report> rep(nsrc);
@@ -2901,7 +3152,7 @@ int ov_correlator_deta(ov_ctx *c, int field, double mass, int nsrc, const void *
         if (dF) *dF = -2.0 * (1.0 - 0.5 * mass) * acc;
     }
     cleanup();
-    return rc;
+    return with_norm_status(c, rc);
 }
 
 }  // extern "C"

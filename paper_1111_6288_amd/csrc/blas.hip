@@ -10,6 +10,25 @@
 
 namespace ov {
 
+// Sum of one double over a workgroup of up to 1024 threads in a fixed order:
+// a butterfly over the 64 lanes of each wave (cross-lane shuffles, no LDS),
+// then the per-wave sums added by wave index.  The result is valid in
+// thread 0.  Every thread of the workgroup must call it.
+__device__ __forceinline__ double block_sum(double v)
+{
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) v += __shfl_xor(v, w, 64);
+    __shared__ double wsum[16];
+    const int wave = (int)(threadIdx.x >> 6), nw = (int)((blockDim.x + 63) >> 6);
+    if ((threadIdx.x & 63) == 0) wsum[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < nw; ++k) s += wsum[k];
+    __syncthreads();
+    return s;
+}
+
 // ---------------------------------------------------------------- packing
 // canonical complex128 [n][V][4][3]  <->  internal field layout [slot]
 template <class S>
@@ -80,14 +99,8 @@ __global__ __launch_bounds__(256) void k_slice_norm2(const double2 *__restrict__
 #pragma unroll
         for (int k = 0; k < 12; ++k) s += p[k].x * p[k].x + p[k].y * p[k].y;
     }
-    __shared__ double sh[256];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[((long)j * Lt + t) * nb + blk] = sh[0];
+    s = block_sum(s);
+    if (threadIdx.x == 0) part[((long)j * Lt + t) * nb + blk] = s;
 }
 
 // out[j Lt + t] = sum_blk part[(j Lt + t) nb + blk]  (fixed order)
@@ -155,6 +168,70 @@ __global__ __launch_bounds__(256) void k_link_row3_dev(const double2 *__restrict
     if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(worst));
 }
 
+// How far the links that the FP32 and BF16 kernels apply are from the
+// uploaded FP64 links: out[2 p + r] = max over links of the Frobenius norm of
+// U_eff - U for p = 0 (FP32 storage), 1 (BF16 storage) and r = 0 (nine
+// entries read), 1 (rows 0, 1 read, row 2 rebuilt as conj(u_0 x u_1)).  The
+// stored entries are rounded exactly as the packing kernel rounds them; the
+// rebuild is evaluated in FP64 here (the kernels' FP32 evaluation adds at
+// most a few FP32 ulps, which the caller allows for).  Since the Frobenius
+// norm bounds the spectral one, ||H_w(U_eff)|| <= ||H_w(U)|| + 4 out[.].
+__device__ __forceinline__ double2 round_store(double2 v, int p)
+{
+    if (p == 0) return make_double2((double)(float)v.x, (double)(float)v.y);
+    const uint32_t w = f2bf((float)v.x) | (f2bf((float)v.y) << 16);
+    return make_double2((double)bf16_lo(w), (double)bf16_hi(w));
+}
+
+__global__ __launch_bounds__(256) void k_link_round_dev(const double2 *__restrict__ U, long nl,
+                                                        unsigned long long *out)
+{
+    double worst[4] = {0, 0, 0, 0};
+    for (long l = blockIdx.x * (long)blockDim.x + threadIdx.x; l < nl; l += (long)gridDim.x * blockDim.x) {
+        const double2 *m = U + 9 * l;
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            double2 r[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) r[k] = round_store(m[k], p);
+            double top = 0, full = 0, reb = 0;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const double dx = r[k].x - m[k].x, dy = r[k].y - m[k].y;
+                top += dx * dx + dy * dy;
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double dx = r[6 + a].x - m[6 + a].x, dy = r[6 + a].y - m[6 + a].y;
+                full += dx * dx + dy * dy;
+                const int b = (a + 1) % 3, c = (a + 2) % 3;
+                const double2 pb = r[b], qc = r[3 + c], pc = r[c], qb = r[3 + b];
+                const double tr = (pb.x * qc.x - pb.y * qc.y) - (pc.x * qb.x - pc.y * qb.y);
+                const double ti = (pb.x * qc.y + pb.y * qc.x) - (pc.x * qb.y + pc.y * qb.x);
+                const double ex = tr - m[6 + a].x, ey = -ti - m[6 + a].y;
+                reb += ex * ex + ey * ey;
+            }
+            worst[2 * p] = fmax(worst[2 * p], sqrt(top + full));
+            worst[2 * p + 1] = fmax(worst[2 * p + 1], sqrt(top + reb));
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double v = worst[i];
+        for (int w = 32; w >= 1; w >>= 1) v = fmax(v, __shfl_xor(v, w, 64));
+        if ((threadIdx.x & 63) == 0) atomicMax(out + i, (unsigned long long)__double_as_longlong(v));
+    }
+}
+
+hipError_t launch_link_round_dev(const double2 *U, long nl, unsigned long long *out, hipStream_t st)
+{
+    long nb = (nl + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_link_round_dev, dim3(nb), dim3(256), 0, st, U, nl, out);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- lincomb
 // out_s = sum_j coef_j(s) * G_j in_j,s   (G_j = gamma5 if bit j of g5mask)
 // optionally red[s][blk] = sum |out_s|^2 over this block's elements.
@@ -197,14 +274,8 @@ __global__ __launch_bounds__(256) void k_lincomb(LcArgs<SI, SO> a)
             for (long r = tid; r < 2L * a.Vp; r += nth) elem(ppos<SI>(p, r, a.Vp), ppos<SO>(p, r, a.Vp), p >= 3);
     }
     if (a.red) {
-        __shared__ double sh[256];
-        sh[threadIdx.x] = nrm;
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) a.red[(long)j * gridDim.x + blockIdx.x] = sh[0];
+        nrm = block_sum(nrm);
+        if (threadIdx.x == 0) a.red[(long)j * gridDim.x + blockIdx.x] = nrm;
     }
 }
 
@@ -232,18 +303,8 @@ __global__ __launch_bounds__(256) void k_dot(const SA *__restrict__ a, long astr
         for (int p = 0; p < 6; ++p)
             for (long r = tid; r < 2L * Vp; r += nth) elem(ppos<SA>(p, r, Vp), ppos<SB>(p, r, Vp), p >= 3);
     }
-    __shared__ double shr[256], shi[256];
-    shr[threadIdx.x] = acc.x;
-    shi[threadIdx.x] = acc.y;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            shr[threadIdx.x] += shr[threadIdx.x + w];
-            shi[threadIdx.x] += shi[threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[(long)j * gridDim.x + blockIdx.x] = make_double2(shr[0], shi[0]);
+    const double re = block_sum(acc.x), im = block_sum(acc.y);
+    if (threadIdx.x == 0) part[(long)j * gridDim.x + blockIdx.x] = make_double2(re, im);
 }
 
 // out[slot(j)] = sum_b part[j][b] in a fixed order (one workgroup per j)
@@ -251,40 +312,25 @@ __global__ void k_reduce_c(const double2 *__restrict__ part, int nb, int n, doub
 {
     const int j = blockIdx.x;
     if (j >= n) return;
-    __shared__ double shr[256], shi[256];
     double r = 0, i = 0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         double2 v = part[(long)j * nb + b];
         r += v.x;
         i += v.y;
     }
-    shr[threadIdx.x] = r;
-    shi[threadIdx.x] = i;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            shr[threadIdx.x] += shr[threadIdx.x + w];
-            shi[threadIdx.x] += shi[threadIdx.x + w];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[oslots ? oslots[j] : j] = make_double2(shr[0], shi[0]);
+    r = block_sum(r);
+    i = block_sum(i);
+    if (threadIdx.x == 0) out[oslots ? oslots[j] : j] = make_double2(r, i);
 }
 
 __global__ void k_reduce_r(const double *__restrict__ part, int nb, int n, double *out, const int *oslots)
 {
     const int j = blockIdx.x;
     if (j >= n) return;
-    __shared__ double sh[256];
     double r = 0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) r += part[(long)j * nb + b];
-    sh[threadIdx.x] = r;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[oslots ? oslots[j] : j] = sh[0];
+    r = block_sum(r);
+    if (threadIdx.x == 0) out[oslots ? oslots[j] : j] = r;
 }
 
 // ---------------------------------------------------------------- CG scalars
@@ -301,9 +347,12 @@ __global__ void k_cg_alpha(const double *rr, const double2 *pAp, const int *acti
     alpha_neg[j] = make_double2(-al, 0.0);
 }
 
-// beta_j = rr_new / rr_old; rr_old <- rr_new; deactivate when rr_new <= stop_j.
+// beta_j = rr_new / rr_old; rr_old <- rr_new; deactivate when rr_new <= stop_j
+// (a NaN residual deactivates too).  iters_j (optional) counts the
+// iterations completed while active, so the host may read the active flags
+// late without losing the per-RHS counts.
 __global__ void k_cg_beta(const double *rr_new, double *rr, int *active, const double *stop, int n,
-                          double2 *beta)
+                          double2 *beta, int *iters)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
@@ -312,8 +361,41 @@ __global__ void k_cg_beta(const double *rr_new, double *rr, int *active, const d
         be = rr[j] > 0.0 ? rr_new[j] / rr[j] : 0.0;
         rr[j] = rr_new[j];
         if (!(rr_new[j] > stop[j])) active[j] = 0;
+        if (iters) iters[j] += 1;
     }
     beta[j] = make_double2(be, 0.0);
+}
+
+// p[0..n) = v (a fill kernel: unlike a memset node it is safe inside a captured graph)
+__global__ void k_fill_int(int *p, int n, int v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Norm check of the sign pipeline.  For a Hermitian Q with spectrum in
+// [-1, 1], ||Q P(Q^2) chi|| <= M ||chi|| with M = max_{|q| <= 1} |q P(q^2)|;
+// bound2 = (slack M)^2.  A right-hand side whose w = Q P(Q^2) chi violates
+// the bound (or whose norms are not finite) sets *flag: the polynomial was
+// evaluated outside [-1, 1], i.e. the norm bound is below ||H_w||.
+__global__ void k_norm_breach(const double2 *chi2, const double2 *w2, const int *oslots, int n, double bound2,
+                              int *flag)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int s = oslots ? oslots[j] : j;
+    const double c = chi2[s].x, w = w2[s].x;
+    if (!(w <= bound2 * c) && !(w == 0.0 && c == 0.0)) *flag = 1;
+}
+
+// G[t] = sum_j part[j Lt + t] over the n rows in order j = 0, 1, ...
+__global__ void k_sum_rows(const double *__restrict__ part, int n, int Lt, double *__restrict__ G)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Lt) return;
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += part[(long)j * Lt + t];
+    G[t] = s;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -425,9 +507,30 @@ hipError_t launch_cg_alpha(const double *rr, const double2 *pAp, const int *acti
 }
 
 hipError_t launch_cg_beta(const double *rr_new, double *rr, int *active, const double *stop, int n,
-                          double2 *beta, hipStream_t st)
+                          double2 *beta, int *iters, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cg_beta, dim3((n + 63) / 64), dim3(64), 0, st, rr_new, rr, active, stop, n, beta);
+    hipLaunchKernelGGL(k_cg_beta, dim3((n + 63) / 64), dim3(64), 0, st, rr_new, rr, active, stop, n, beta, iters);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_breach(const double2 *chi2, const double2 *w2, const int *oslots, int n, double bound2,
+                              int *flag, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_norm_breach, dim3((n + 63) / 64), dim3(64), 0, st, chi2, w2, oslots, n, bound2, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_rows(const double *part, int n, int Lt, double *G, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum_rows, dim3((Lt + 255) / 256), dim3(256), 0, st, part, n, Lt, G);
     return hipGetLastError();
 }
 

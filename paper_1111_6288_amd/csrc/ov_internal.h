@@ -67,7 +67,13 @@ hipError_t launch_reduce_r(const double *part, int nb, int n, double *out, const
 hipError_t launch_cg_alpha(const double *rr, const double2 *pAp, const int *active, int n, double2 *ap,
                            double2 *an, hipStream_t st);
 hipError_t launch_cg_beta(const double *rr_new, double *rr, int *active, const double *stop, int n,
-                          double2 *beta, hipStream_t st);
+                          double2 *beta, int *iters, hipStream_t st);
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t st);
+// *flag = 1 if some RHS j has w2[slot j] > bound2 * chi2[slot j] (or a non-finite norm)
+hipError_t launch_norm_breach(const double2 *chi2, const double2 *w2, const int *oslots, int n, double bound2,
+                              int *flag, hipStream_t st);
+// G[t] = sum_{j < n} part[j Lt + t] in order of j
+hipError_t launch_sum_rows(const double *part, int n, int Lt, double *G, hipStream_t st);
 
 template <class S>
 hipError_t launch_pack_spinor(const double2 *in, S *out, long fstride, const int *slots, int n, int V, int Vp,
@@ -82,6 +88,10 @@ hipError_t launch_count_nonfinite(const double *p, long n, int *count, hipStream
 // max_a |u_2a - conj(u_0b u_1c - u_0c u_1b)|, as the bits of a non-negative
 // double atomically maxed into *out (which the caller clears).
 hipError_t launch_link_row3_dev(const double2 *U, long nl, unsigned long long *out, hipStream_t st);
+// out[2 p + r]: max Frobenius distance between the stored links and the links
+// the kernels apply for p = 0 FP32 / 1 BF16 storage, r = 0 nine entries /
+// 1 two rows and the rebuilt third; maxed atomically (caller clears).
+hipError_t launch_link_round_dev(const double2 *U, long nl, unsigned long long *out, hipStream_t st);
 
 // ---------------------------------------------------------------- projection
 long proj_dot_chunk(long K);

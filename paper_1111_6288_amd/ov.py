@@ -107,6 +107,11 @@ def _load():
         "ov_set_occupancy": ([vp, i, i], i),
         "ov_get_launch_config": ([vp, i, i, cp(i)], i),
         "ov_set_launch_config": ([vp, i, i, cp(i)], i),
+        "ov_set_norm_check": ([vp, i], i),
+        "ov_norm_status": ([vp], i),
+        "ov_get_sign_norm": ([vp, i, cp(d)], i),
+        "ov_pion_correlator": ([vp, i, vp, cp(d)], i),
+        "ov_ratio_R": ([i, i, cp(d), cp(d), cp(d)], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -124,7 +129,8 @@ EXPORTED = ("ov_create", "ov_destroy", "ov_set_stream", "ov_last_error", "ov_upl
             "ov_set_site_order", "ov_set_occupancy", "ov_get_launch_config",
             "ov_set_launch_config", "ov_hw_eigensolve", "ov_dense_heev", "ov_multishift_cg",
             "ov_dov_eigensolve", "ov_timeslice_norm2", "ov_correlator_deta", "ov_set_link_reconstruct",
-            "ov_get_link_format")
+            "ov_get_link_format", "ov_set_norm_check", "ov_norm_status", "ov_get_sign_norm",
+            "ov_pion_correlator", "ov_ratio_R")
 
 
 def _ints(v):
@@ -165,11 +171,21 @@ def dense_heev(A):
     return w, Z.view(np.complex128).reshape(n, n).T.copy()
 
 
-def ratio_R(G_E, G_0):
-    """R(t) = G_E(t) / G_0(t) (Sec. 4): G_E from the field runs (average of u and d at +E and -E),
-    G_0 without field."""
+def ratio_R(G_E_all, G_0):
+    """R(t) = mean_e G_E_all[e](t) / G_0(t) (ov_ratio_R, Sec. 4): G_E_all holds the correlators of the
+    field runs (u and d at +E and -E), G_0 the one without field."""
     import numpy as np
-    return np.asarray(G_E, dtype=float) / np.asarray(G_0, dtype=float)
+    ge = np.ascontiguousarray(np.atleast_2d(np.asarray(G_E_all, dtype=np.float64)))
+    g0 = np.ascontiguousarray(np.asarray(G_0, dtype=np.float64))
+    lt = int(g0.shape[0])
+    if ge.shape[1] != lt:
+        raise ValueError(f"G_E_all has {ge.shape[1]} time slices, G_0 has {lt}")
+    out = np.zeros(lt)
+    pd = C.POINTER(C.c_double)
+    rc = lib.ov_ratio_R(lt, int(ge.shape[0]), ge.ctypes.data_as(pd), g0.ctypes.data_as(pd), out.ctypes.data_as(pd))
+    if rc != OV_OK:
+        raise OvError(rc, "ov_ratio_R: bad correlators")
+    return out
 
 
 class Context:
@@ -385,9 +401,29 @@ class Context:
         return Ct, dF.value
 
     def pion_correlator(self, props):
-        """Connected pseudoscalar correlator of one flavour, G(t) = sum over the 12 point-source
-        propagators (props: (12, V, 4, 3)) and the sink spin-colour of |S|^2 (gamma5-hermiticity)."""
-        return self.timeslice_norm2(props).sum(axis=0)
+        """Connected pseudoscalar correlator of one flavour (ov_pion_correlator): G(t) = sum over the
+        point-source propagators (props: (nsrc, V, 4, 3)) and the sink spin-colour of |S|^2."""
+        import numpy as np
+        props = props.reshape(-1, self.V, 4, 3).contiguous()
+        G = np.zeros(self.L[3])
+        self._chk(lib.ov_pion_correlator(self._h, int(props.shape[0]), _dev(props, (self.V, 4, 3), "props"),
+                                         G.ctypes.data_as(C.POINTER(C.c_double))))
+        return G
+
+    def set_norm_check(self, mode):
+        """0: off; 1: breaches reported by synchronising calls and norm_status(); 2 (default): sign and
+        D(m) applies also synchronise and raise OV_ENORM."""
+        return self._chk(lib.ov_set_norm_check(self._h, int(mode)))
+
+    def norm_status(self):
+        """Raise OvError(OV_ENORM) if a sign application since the last check exceeded its growth bound."""
+        return self._chk(lib.ov_norm_status(self._h))
+
+    def sign_norm(self, prec="fp64"):
+        """Norm the sign pipeline of `prec` divides H_w by (the set norm plus the link-rounding margin)."""
+        v = C.c_double(0.0)
+        self._chk(lib.ov_get_sign_norm(self._h, PREC[prec], C.byref(v)))
+        return v.value
 
     def hw_eigensolve(self, field, l, k=None, cheb_order=60, cutoff=0.0, max_iter=20, tol=1e-10, prec="fp64",
                       x0=None, seed=0, install=True, want_vectors=True, raise_on_noconv=True):
