@@ -30,6 +30,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -62,8 +64,10 @@ def parse():
     p.add_argument("--eig", action="store_true",
                    help="also time the H_w low-mode eigensolver at 24^3x48 (adds an 'eigensolver' object)")
     p.add_argument("--eig-l", type=int, default=LSMALL)
+    p.add_argument("--no-tts", action="store_true",
+                   help="skip the default time-to-solution comparison (mixed vs FP64 inner CG at 1e-10)")
     p.add_argument("--tts", action="store_true",
-                   help="also time propagators at 16^3x32: per-mass CG vs multi-mass sector CG")
+                   help="also time propagator methods at 16^3x32: per-mass CG vs multi-mass sector CG")
     p.add_argument("--tts-l", type=int, default=100)
     p.add_argument("--tts-ldov", type=int, default=16)
     p.add_argument("--eig-order", type=int, default=100)
@@ -213,6 +217,68 @@ def eig_measurement(torch, ov, U, args):
             "kernels_ms": {c: round(v[1], 1) for c, v in prof.items()}}
 
 
+def tts_mixed_vs_fp64(torch, ov):
+    """Time to solution at 1e-10 (Sec. 3.2: FP32 late in the solve, FP64 defect correction).
+
+    16^3 x 32, Dirichlet x and t, one operator (q eta = 2/3 x 1e-3): the 64 lowest H_w modes
+    from the eigensolver (timed apart), eps and the order n from eq. (2) for delta = 1e-10 at
+    0.95 |lambda_64|, then 12 propagators (4 point sources x masses 0.05, 0.1, 0.2) in one batch
+    to an FP64 true residual of 1e-10: once with FP32 inner / FP64 outer CG, once with FP64 inner
+    CG.  Reports both times, the inner iterations, and per propagator the relative difference of
+    the two solutions and the FP64 residuals both reached."""
+    import math
+
+    import synth
+
+    Lt = (16, 16, 16, 32)
+    U = synth.su3_links(Lt, 0.2, 2016)
+    ctx = ov.Context(Lt, BC, MW)
+    ctx.upload_gauge(torch.from_numpy(U).cuda())
+    ctx.set_fields([Q], [1e-3])
+    ctx.set_sign_params(100, 0.01, NORM)
+    l = 64
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lam, res, _, rep = ctx.hw_eigensolve(0, l, k=80, cheb_order=100, tol=1e-10, prec="fp32", seed=3,
+                                         install=True, want_vectors=False)
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    lam_l = max(abs(v) for v in lam)
+    eps = (0.95 * lam_l / NORM) ** 2
+    n = int(math.ceil(math.log(0.41 / 1e-10) / (2.1 * math.sqrt(eps))))
+    ctx.set_sign_params(n, eps, NORM)
+    src = synth.point_sources(Lt, (8, 0, 0, 16))[[0, 4, 7, 11]]
+    masses = (0.05, 0.1, 0.2)
+    b = torch.from_numpy(np.concatenate([src] * len(masses))).cuda()
+    mvec = [m for m in masses for _ in range(len(src))]
+    print(f"[bench] tts: eigensolve {t_eig:.1f}s, n = {n}, eps = {eps:.3e}", file=sys.stderr, flush=True)
+    out = {}
+    for inner in ("fp32", "fp64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, report = ctx.deflated_cg(b, mass=mvec, tol=1e-10, inner_prec=inner,
+                                    inner_tol=1e-5 if inner == "fp32" else 1e-11, use_deflation=False)
+        torch.cuda.synchronize()
+        out[inner] = (time.perf_counter() - t0, x, report)
+        print(f"[bench] tts: {inner} inner CG {out[inner][0]:.1f}s", file=sys.stderr, flush=True)
+    x32, x64 = out["fp32"][1], out["fp64"][1]
+    diff = ((x32 - x64).reshape(len(mvec), -1).norm(dim=1) / x64.reshape(len(mvec), -1).norm(dim=1)).tolist()
+    ctx.close()
+
+    def summary(k):
+        t, _, r = out[k]
+        return {"seconds": round(t, 2), "inner_iters_summed": sum(e["iters"] for e in r),
+                "max_inner_iters": max(e["iters"] for e in r), "fp64_restarts_max": max(e["restarts"] for e in r),
+                "max_relres": max(e["relres"] for e in r)}
+
+    return {"workload": "16^3x32 Dirichlet x,t; q eta = 2/3 x 1e-3; 64 H_w low modes; 12 propagators "
+                        "(4 point sources x masses 0.05, 0.1, 0.2) in one batch to FP64 true residual 1e-10",
+            "npoly": n, "eps": eps, "eig_seconds": round(t_eig, 2), "lambda_64": lam_l,
+            "mixed_fp32_inner": summary("fp32"), "fp64_inner": summary("fp64"),
+            "speedup_mixed_vs_fp64": round(out["fp64"][0] / out["fp32"][0], 3),
+            "mixed_vs_fp64_solution_rel_diff": {"max": max(diff), "per_propagator": [float(f"{d:.3e}") for d in diff]}}
+
+
 def tts_measurement(torch, ov, args):
     """Time to solution at 16^3 x 32, one operator (q eta = 2/3 x 1e-3): H_w low modes by the
     eigensolver, eps and n from lambda_l by eq. (2) for delta = 1e-10, then propagators of
@@ -303,41 +369,75 @@ def tts_measurement(torch, ov, args):
             "speedup_deflation": round(t_pm / t_pmd, 2)}
 
 
+CPU_SAMPLE = r"""
+import json, sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import synth
+from oracle import api
+L, BC, MW, EPS, NORM, QE, M, SRC = json.loads(sys.argv[2])
+runs = json.loads(sys.argv[3])
+U = synth.su3_links(L, 0.2, 2022)
+lat = api.Lattice(L, BC, MW, U, QE)
+x = synth.point_sources(L, SRC)[0]
+lmax = max(l for _, l in runs)
+Vs = synth.random_orthonormal(L, lmax, 9) if lmax else None
+api.dov(lat, api.SignParams(1, EPS, NORM), x, M)
+out = []
+for n, l in runs:
+    sp = api.SignParams(n, EPS, NORM, Vs[:l] if l else None, np.linspace(-1, 1, l) if l else None)
+    t0 = time.perf_counter()
+    api.dov(lat, sp, x, M)
+    out.append(time.perf_counter() - t0)
+print(json.dumps(out))
+"""
+
+
+def _oracle_dov_seconds(runs, threads):
+    """Wall times of FP64 oracle D(m) applications (order n, l small-space vectors, for each
+    (n, l) in runs) on one point source at 24^3 x 48, in a child process with `threads` OpenMP
+    threads (the oracle's thread count is fixed when it loads)."""
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    cfg = json.dumps([list(L), list(BC), MW, EPS, NORM, Q * ETAS[1], MASSES[1], list(SRC)])
+    r = subprocess.run([sys.executable, "-c", CPU_SAMPLE, ROOT, cfg, json.dumps(runs)], env=env,
+                       capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"oracle sample failed: {r.stderr[-2000:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def cpu_baseline():
-    """Bounded sample of the FP64 oracle on the host: D(m) on one RHS at 24^3 x 48.
+    """The FP64 oracle on the host cores: one measured order-300 D(m) at 24^3 x 48.
 
-    Runs the oracle's D(m) with (n, l) = (2, 0), (6, 0) and (2, 8), fits
-    time = a + b n + c l, and reports 1 / (a + 300 b + 200 c) applies/s.
+    Measured: D(m) with n = 300 and an 8-vector small space on one point source, all host
+    threads (the workload's order; only the small space is smaller).  The 200-vector small
+    space is added from two short runs (n = 1 with l = 0 and l = 8: the per-vector projection
+    cost, linear in l).  A 1-thread run of the n = 1, l = 0 sample gives the speed of one core.
     """
-    import numpy as np
-
-    import synth
-    from oracle import api
-
-    U = synth.su3_links(L, 0.2, 2022)
-    lat = api.Lattice(L, BC, MW, U, Q * ETAS[1])
-    x = synth.point_sources(L, SRC)[0]
-    Vs = synth.random_orthonormal(L, 8, 9)
-    lam = np.linspace(-1, 1, 8)
-
-    def run(n, l):
-        sp = api.SignParams(n, EPS, NORM, Vs[:l] if l else None, lam[:l] if l else None)
-        t0 = time.perf_counter()
-        api.dov(lat, sp, x, MASSES[1])
-        return time.perf_counter() - t0
-
-    run(1, 0)
-    t20, t60, t28 = run(2, 0), run(6, 0), run(2, 8)
-    b = (t60 - t20) / 4.0
-    a = t20 - 2 * b
-    cvec = max(t28 - t20, 0.0) / 8.0
-    t_apply = a + NPOLY * b + LSMALL * cvec
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t300, t1_0, t1_8 = _oracle_dov_seconds([[NPOLY, 8], [1, 0], [1, 8]], threads)
+    per_vec = max(t1_8 - t1_0, 0.0) / 8.0
+    t_apply = t300 + (LSMALL - 8) * per_vec
+    (one,) = _oracle_dov_seconds([[1, 0]], 1)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
-        "value": 1.0 / t_apply, "unit": "D_ov applies/s", "cores": cores, "kind": "oracle",
-        "sample": (f"FP64 oracle D(m) on 1 point source at 24^3x48, timed at (n,l)=(2,0),(6,0),(2,8) "
-                   f"[{t20:.2f}s, {t60:.2f}s, {t28:.2f}s], scaled linearly to n=300, l=200: "
-                   f"{t_apply:.1f} s per apply"),
+        "value": 1.0 / t_apply, "unit": "D_ov applies/s", "cores": threads, "kind": "oracle",
+        "sample": (f"FP64 oracle D(m), n=300, l=8, 1 point source at 24^3x48 on {threads} threads: "
+                   f"{t300:.1f} s measured; + 192 small-space vectors at {per_vec:.3f} s each "
+                   f"(n=1 runs with l=0/8: {t1_0:.2f}/{t1_8:.2f} s) = {t_apply:.1f} s per apply"),
+        "cpu_model": model, "nproc": os.cpu_count(),
+        "one_thread": {"n1_l0_seconds": round(one, 3), "n1_l0_seconds_all_threads": round(t1_0, 3),
+                       "parallel_speedup": round(one / max(t1_0, 1e-9), 2),
+                       "est_seconds_per_apply": round(t_apply * one / max(t1_0, 1e-9), 1)},
     }
 
 
@@ -458,13 +558,14 @@ def main():
         "cpu_baseline": cpu,
     }
     ctx.close()
-    if args.eig or args.tts:
-        del x, y32
-        torch.cuda.empty_cache()
+    del x, y32
+    torch.cuda.empty_cache()
+    if not args.no_tts:
+        line["time_to_solution"] = tts_mixed_vs_fp64(torch, ov)
     if args.eig:
         line["eigensolver"] = eig_measurement(torch, ov, U, args)
     if args.tts:
-        line["time_to_solution"] = tts_measurement(torch, ov, args)
+        line["propagator_methods"] = tts_measurement(torch, ov, args)
     print(json.dumps(line), flush=True)
     if args.calibrate_copy:
         src = torch.empty(4 << 30, dtype=torch.uint8, device="cuda").fill_(1)
