@@ -165,6 +165,24 @@ int ov_dslash(ov_ctx *ctx, int prec, int op, int nrhs, const int *field_of_rhs,
               const void *x_dev, void *y_dev);
 
 /*
+ * ov_dslash for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same operation, arguments and kernels as ov_dslash, with the packed
+ * input, the packed output and the field-group list held in one fixed
+ * device array of 64 MiB per GPU (file-scope in the library, resident until
+ * the process ends) instead of the context's workspace.  It calls no
+ * hipMalloc / hipFree and records no profiling events; it copies
+ * field_of_rhs to the device and synchronises the stream once before the
+ * launch.  Size limit: 256 + 2 * nrhs * 12 * Vp * S bytes <= 64 MiB, with
+ * Vp = V rounded up to a multiple of 64 and S = 16 (FP64), 8 (FP32),
+ * 4 (BF16); larger requests return OV_EINVAL and touch nothing.  Every call
+ * on a GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (other threads, other streams) race; calls ordered on one stream do not.
+ */
+int ov_dslash_noalloc(ov_ctx *ctx, int prec, int op, int nrhs, const int *field_of_rhs, const void *x_dev,
+                      void *y_dev);
+
+/*
  * y = s(x) = V sgn(lambda) V^dag x + Pi Q P(Q^2) Pi x with Pi = 1 - V V^dag
  * (Sec. 2: small space exact, polynomial on the rest), per RHS with the small
  * space of its group.  Cost: 2n+1 H_w applications.  x_dev, y_dev as in

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -29,6 +30,10 @@
 #include "ov_internal.h"
 
 using namespace ov;
+
+// Fixed device scratch of ov_dslash_noalloc (see scratch_init below).
+constexpr size_t kScratchBytes = 64ul << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -121,6 +126,9 @@ struct ov_ctx {
     int *h_pin = nullptr;
     size_t h_pin_n = 0;
     hipEvent_t ev_mask[2] = {nullptr, nullptr};
+
+    // device address of the fixed scratch array of ov_dslash_noalloc on this device
+    void *scratch = nullptr;
 
     size_t mem_bytes = 0;
 
@@ -920,6 +928,37 @@ int api_dslash(ov_ctx *c, int op, int nrhs, const std::vector<int> &grp, const v
     return OV_OK;
 }
 
+// ov_dslash on the fixed scratch array instead of the arena: the field-group
+// list, the packed input and the packed output live there.  No allocation:
+// no arena growth, no cached device lists, no profiling events.
+template <class S>
+int api_dslash_noalloc(ov_ctx *c, int op, int nrhs, const std::vector<int> &grp, const void *x, void *y)
+{
+    const size_t ib = align_up(sizeof(int) * nrhs);
+    const size_t fb = align_up(field_bytes<S>(c) * nrhs);
+    if (ib + 2 * fb > kScratchBytes)
+        return fail(c, OV_EINVAL, "ov_dslash_noalloc: %d RHS of %d sites need %zu bytes of scratch, the limit is %zu",
+                    nrhs, c->g.V, ib + 2 * fb, kScratchBytes);
+    char *base = (char *)c->scratch;
+    int *fg = (int *)base;
+    S *X = (S *)(base + ib);
+    S *Y = (S *)(base + ib + fb);
+    HIPCHK(h2d(c, fg, grp.data(), sizeof(int) * nrhs));
+    Batch b;
+    b.n = nrhs;
+    b.slots = nullptr;
+    HIPCHK(launch_pack_spinor<S>((const double2 *)x, X, (long)field_elems(c), nullptr, nrhs, c->g.V, c->g.Vp,
+                                 c->stream));
+    const bool prof = c->prof_on;
+    c->prof_on = false;
+    const int rc = dslash_launch<S>(c, b, fg, X, Y, 1.0, op == OV_OP_HW);
+    c->prof_on = prof;
+    CHK(rc);
+    HIPCHK(launch_unpack_spinor<S>(Y, (double2 *)y, (long)field_elems(c), nullptr, nrhs, c->g.V, c->g.Vp,
+                                   c->stream));
+    return OV_OK;
+}
+
 template <class S>
 int api_sign(ov_ctx *c, int nrhs, const std::vector<int> &grp, const void *x, void *y)
 {
@@ -964,6 +1003,34 @@ int api_dov(ov_ctx *c, int nrhs, const std::vector<int> &grp, const double *mass
     return c->norm_check == 2 ? take_norm_flag(c) : OV_OK;
 }
 
+// ---------------------------------------------------------------- fixed scratch
+// Device memory of the allocation-free entry point ov_dslash_noalloc: one
+// array per GPU, held for the life of the process.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address that hipGetSymbolAddress returns for
+// the current device, kept per device in g_scratch.
+constexpr int kMaxDevices = 64;
+void *g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Called by ov_create with the context's device current.
+int scratch_init(ov_ctx *c)
+{
+    if (c->device >= kMaxDevices) return OV_OK;   // ov_dslash_noalloc then reports OV_ESTATE
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[c->device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(c, OV_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        }
+        g_scratch[c->device] = p;
+    }
+    c->scratch = g_scratch[c->device];
+    return OV_OK;
+}
+
 }  // namespace
 
 // ======================================================================== C ABI
@@ -1005,7 +1072,7 @@ int ov_create(const int32_t L[4], const int32_t bc[4], double m_w, int device, o
         delete c;
         return OV_ENOMEM;
     }
-    if (hipMemset(c->d_count, 0, 256) != hipSuccess) {
+    if (hipMemset(c->d_count, 0, 256) != hipSuccess || scratch_init(c) != OV_OK) {
         (void)hipFree(c->d_count);
         delete c;
         return OV_EHIP;
@@ -1236,6 +1303,21 @@ int ov_dslash(ov_ctx *c, int prec, int op, int nrhs, const int *field_of_rhs, co
     if (prec == OV_FP64) return api_dslash<double2>(c, op, nrhs, grp, x, y);
     if (prec == OV_FP32) return api_dslash<float2>(c, op, nrhs, grp, x, y);
     return api_dslash<uint32_t>(c, op, nrhs, grp, x, y);
+}
+
+int ov_dslash_noalloc(ov_ctx *c, int prec, int op, int nrhs, const int *field_of_rhs, const void *x, void *y)
+{
+    CHK(check_ctx(c));
+    CHK(check_prec(c, prec));
+    if (op != OV_OP_DW && op != OV_OP_HW) return fail(c, OV_EINVAL, "unknown operator %d", op);
+    if (!x || !y) return fail(c, OV_EINVAL, "null spinor pointer");
+    if (!c->have_gauge) return fail(c, OV_ESTATE, "no gauge field uploaded");
+    if (!c->scratch) return fail(c, OV_ESTATE, "no fixed scratch on device %d", c->device);
+    std::vector<int> grp;
+    CHK(check_fields(c, nrhs, field_of_rhs, grp));
+    if (prec == OV_FP64) return api_dslash_noalloc<double2>(c, op, nrhs, grp, x, y);
+    if (prec == OV_FP32) return api_dslash_noalloc<float2>(c, op, nrhs, grp, x, y);
+    return api_dslash_noalloc<uint32_t>(c, op, nrhs, grp, x, y);
 }
 
 int ov_set_norm_check(ov_ctx *c, int mode)

@@ -107,6 +107,7 @@ def _load():
         "ov_set_occupancy": ([vp, i, i], i),
         "ov_get_launch_config": ([vp, i, i, cp(i)], i),
         "ov_set_launch_config": ([vp, i, i, cp(i)], i),
+        "ov_dslash_noalloc": ([vp, i, i, i, cp(i), vp, vp], i),
         "ov_set_norm_check": ([vp, i], i),
         "ov_norm_status": ([vp], i),
         "ov_get_sign_norm": ([vp, i, cp(d)], i),
@@ -129,7 +130,7 @@ EXPORTED = ("ov_create", "ov_destroy", "ov_set_stream", "ov_last_error", "ov_upl
             "ov_set_site_order", "ov_set_occupancy", "ov_get_launch_config",
             "ov_set_launch_config", "ov_hw_eigensolve", "ov_dense_heev", "ov_multishift_cg",
             "ov_dov_eigensolve", "ov_timeslice_norm2", "ov_correlator_deta", "ov_set_link_reconstruct",
-            "ov_get_link_format", "ov_set_norm_check", "ov_norm_status", "ov_get_sign_norm",
+            "ov_get_link_format", "ov_dslash_noalloc", "ov_set_norm_check", "ov_norm_status", "ov_get_sign_norm",
             "ov_pion_correlator", "ov_ratio_R")
 
 
@@ -409,6 +410,15 @@ class Context:
         self._chk(lib.ov_pion_correlator(self._h, int(props.shape[0]), _dev(props, (self.V, 4, 3), "props"),
                                          G.ctypes.data_as(C.POINTER(C.c_double))))
         return G
+
+    def dslash_noalloc(self, x, fields=None, op="HW", prec="fp64", out=None):
+        """ov_dslash on the library's fixed scratch array (no device allocation inside the call)."""
+        x, n, fields = self._io(x, fields)
+        y = torch.empty_like(x) if out is None else out
+        opc = OV_OP_HW if op == "HW" else OV_OP_DW
+        self._chk(lib.ov_dslash_noalloc(self._h, PREC[prec], opc, n, _ints(fields), _dev(x, (self.V, 4, 3), "x"),
+                                        _dev(y, (self.V, 4, 3), "y")))
+        return y
 
     def set_norm_check(self, mode):
         """0: off; 1: breaches reported by synchronising calls and norm_status(); 2 (default): sign and
