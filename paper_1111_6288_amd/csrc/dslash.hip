@@ -222,19 +222,32 @@ struct GlobalLinks {   // straight from the packed link field
     }
 };
 
-template <class R, bool REC, int SL>
-struct LdsLinks {   // staged in LDS by the workgroup: [slot][component][site slot], SL site slots
+// Staged in LDS by the workgroup: [slot][component][site slot], SL site
+// slots, E components per link (9, or 6 when the third row is rebuilt at
+// each read: RB).
+template <class R, int E, bool RB, int SL>
+struct LdsLinks {
     const cx<R> *base;
     int sl;   // this thread's site slot
     __device__ __forceinline__ void operator()(int, int slot, unsigned, cx<R> (&u)[3][3]) const
     {
-        constexpr int E = REC ? 6 : 9;
         const cx<R> *p = base + slot * E * SL + sl;
 #pragma unroll
         for (int k = 0; k < E; ++k) u[k / 3][k % 3] = p[k * SL];
-        if constexpr (REC) rebuild_row2(u);
+        if constexpr (RB) rebuild_row2(u);
     }
 };
+
+// Components a link occupies in the LDS stage.  Links with FP32 arithmetic
+// are rebuilt once, when the workgroup stages them, and stored whole (every
+// wave of the workgroup would otherwise repeat the six complex products of
+// the third row for each of its eight links); FP64 keeps two rows (nine FP64
+// components per link would halve the resident workgroups).
+template <class R, bool REC>
+__host__ __device__ constexpr int lds_link_components()
+{
+    return (REC && sizeof(R) == 8) ? 6 : 9;
+}
 
 // One direction, both hops, for all NR right-hand sides of this thread.
 template <int MU, int NR, class S, class R, class LF>
@@ -384,7 +397,24 @@ __device__ __forceinline__ int dslash_site(const Geo &g, int order, int xcd_rema
 // Q == 1 means j0 is uniform over the wave, which lets the RHS offsets live
 // in scalar registers.
 template <class S, int NR, int Q, bool HW, bool EPI, class LF>
+__device__ __forceinline__ void dslash_body_at(const DsArgs<S> &a, int site, int xc, int yc, int zc, int tc, int j0,
+                                               const LF &lf);
+
+template <class S, int NR, int Q, bool HW, bool EPI, class LF>
 __device__ __forceinline__ void dslash_body(const DsArgs<S> &a, int site, int j0, const LF &lf)
+{
+    int rem = site;
+    const int xc = rem % a.g.Lx; rem /= a.g.Lx;
+    const int yc = rem % a.g.Ly; rem /= a.g.Ly;
+    const int zc = rem % a.g.Lz;
+    const int tc = rem / a.g.Lz;
+    dslash_body_at<S, NR, Q, HW, EPI>(a, site, xc, yc, zc, tc, j0, lf);
+}
+
+// The body for a site whose coordinates are known.
+template <class S, int NR, int Q, bool HW, bool EPI, class LF>
+__device__ __forceinline__ void dslash_body_at(const DsArgs<S> &a, int site, int xc, int yc, int zc, int tc, int j0,
+                                               const LF &lf)
 {
     using R = typename StoreT<S>::real;
     const Geo &g = a.g;
@@ -413,12 +443,6 @@ __device__ __forceinline__ void dslash_body(const DsArgs<S> &a, int site, int j0
         }
         return;
     }
-
-    int rem = site;
-    const int xc = rem % g.Lx; rem /= g.Lx;
-    const int yc = rem % g.Ly; rem /= g.Ly;
-    const int zc = rem % g.Lz;
-    const int tc = rem / g.Lz;
 
     cx<R> ph[NR];
 #pragma unroll
@@ -467,44 +491,39 @@ __global__ __launch_bounds__(256) void k_dslash(DsArgs<S> a)
 // Link-sharing variant.  The W waves of a workgroup (W = blockDim / 64: 2, 4
 // or 8) cover the same 64/Q sites, each for its own Q NR right-hand sides, so
 // a workgroup covers 64/Q sites for W Q NR RHS.  Before the stencil the
-// workgroup copies the eight links its sites use (U_mu(s) and U_mu(s - mu),
-// two or three rows each) into LDS; every wave then reads them there, so a
-// link crosses HBM once per W Q NR RHS rather than once per Q NR, without
-// narrowing the run of consecutive sites each load instruction covers.
-// Threads of padding sites take part in the copy and the barrier and only
-// then leave.
-template <class S, int NR, int Q, bool HW, bool EPI, bool REC>
-__global__ __launch_bounds__(512) void k_dslash_lds(DsArgs<S> a)
+// workgroup copies the eight links its sites use (U_mu(s) and U_mu(s - mu))
+// into LDS; every wave then reads them there, so a link crosses HBM once per
+// W Q NR RHS rather than once per Q NR, without narrowing the run of
+// consecutive sites each load instruction covers.  With two-row links and
+// FP32 arithmetic the stage holds whole links: the third row is rebuilt once
+// per workgroup instead of once per wave.  Threads of padding sites take
+// part in the copy and the barrier and only then leave.
+//
+// Copy one link (site s, its coordinates given; slot 0..3 = U_mu(s), 4..7 =
+// U_mu(s - mu)) into LDS, E components, rebuilding the third row when the
+// stored rows are two (REC) and the stage holds nine (E == 9).
+template <class S, class R, bool REC, int E, int SL>
+__device__ __forceinline__ void stage_link(const DsArgs<S> &a, int slot, int s, int xc, int yc, int zc, int tc,
+                                           cx<R> *dst)
 {
-    using R = typename StoreT<S>::real;
-    constexpr int SL = 64 / Q, E = REC ? 6 : 9;
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    cx<R> *lk = reinterpret_cast<cx<R> *>(lds_raw);   // [8][E][SL]
     const Geo &g = a.g;
-    const int W = (int)(blockDim.x >> 6), wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-
-    for (int idx = (int)threadIdx.x; idx < 8 * SL; idx += (int)blockDim.x) {
-        const int slot = idx / SL, sl = idx - slot * SL;
-        const int s = site_in_block(g, a.order, a.xcd_remap, a.cols, sl, SL);
-        cx<R> *dst = lk + slot * E * SL + sl;
-        if (s >= g.V) {   // padding or beyond the slab: never read
+    const int mu = slot & 3;
+    int src = s;
+    if (slot >= 4) {   // backward neighbour s - mu, wrapping
+        const int c = mu == 0 ? xc : mu == 1 ? yc : mu == 2 ? zc : tc;
+        const int L = mu == 0 ? g.Lx : mu == 1 ? g.Ly : mu == 2 ? g.Lz : g.Lt;
+        const int stride = mu == 0 ? 1 : mu == 1 ? g.Lx : mu == 2 ? g.Lxy : g.Lxyz;
+        src = (c == 0) ? s + (L - 1) * stride : s - stride;
+    }
+    // the same 16-byte pair loads as the other kernels (full cache lines over a
+    // run of consecutive sites)
+    const S *ub = a.U + (size_t)(mu * 9) * (unsigned)g.Vp;
+    if constexpr (REC && E == 9) {
+        cx<R> u[3][3];
+        load_link<S, R, true>(a.U, mu, g.Vp, (unsigned)src, u);   // two rows read, third rebuilt
 #pragma unroll
-            for (int k = 0; k < E; ++k) dst[k * SL] = cmk((R)0, (R)0);
-            continue;
-        }
-        const int mu = slot & 3;
-        int src = s;
-        if (slot >= 4) {   // backward neighbour s - mu, wrapping
-            int c, L, stride;
-            if (mu == 0) { c = s % g.Lx; L = g.Lx; stride = 1; }
-            else if (mu == 1) { c = (s / g.Lx) % g.Ly; L = g.Ly; stride = g.Lx; }
-            else if (mu == 2) { c = (s / g.Lxy) % g.Lz; L = g.Lz; stride = g.Lxy; }
-            else { c = s / g.Lxyz; L = g.Lt; stride = g.Lxyz; }
-            src = (c == 0) ? s + (L - 1) * stride : s - stride;
-        }
-        // the same 16-byte pair loads as the other kernels (full cache lines over a
-        // run of consecutive sites)
-        const S *ub = a.U + (size_t)(mu * 9) * (unsigned)g.Vp;
+        for (int k = 0; k < 9; ++k) dst[k * SL] = u[k / 3][k % 3];
+    } else {
 #pragma unroll
         for (int p = 0; p < E / 2; ++p) {   // components 0..5 (two rows) or 0..7
             cx<R> c0, c1;
@@ -514,16 +533,64 @@ __global__ __launch_bounds__(512) void k_dslash_lds(DsArgs<S> a)
         }
         if constexpr (E == 9) dst[8 * SL] = ldp<S, R>(ub + (size_t)8 * (unsigned)g.Vp, (unsigned)src);
     }
-    __syncthreads();
+}
 
+__device__ __forceinline__ void site_coords(const Geo &g, int s, int &xc, int &yc, int &zc, int &tc)
+{
+    int rem = s;
+    xc = rem % g.Lx; rem /= g.Lx;
+    yc = rem % g.Ly; rem /= g.Ly;
+    zc = rem % g.Lz;
+    tc = rem / g.Lz;
+}
+
+template <class S, int NR, int Q, bool HW, bool EPI, bool REC>
+__global__ __launch_bounds__(512) void k_dslash_lds(DsArgs<S> a)
+{
+    using R = typename StoreT<S>::real;
+    constexpr int SL = 64 / Q, E = lds_link_components<R, REC>();
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    cx<R> *lk = reinterpret_cast<cx<R> *>(lds_raw);   // [8][E][SL]
+    const Geo &g = a.g;
+    const int W = (int)(blockDim.x >> 6), wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
     const int sl = lane & (SL - 1);
     const int site = site_in_block(g, a.order, a.xcd_remap, a.cols, sl, SL);
+    int xc = 0, yc = 0, zc = 0, tc = 0;
+    if (site < g.V) site_coords(g, site, xc, yc, zc, tc);
+
+    if constexpr (Q == 1) {
+        // thread (wave w, lane l) stages slots w, w + W, ... of its own site
+        for (int slot = wave; slot < 8; slot += W) {
+            cx<R> *dst = lk + slot * E * SL + sl;
+            if (site >= g.V) {   // padding or beyond the slab: never read
+#pragma unroll
+                for (int k = 0; k < E; ++k) dst[k * SL] = cmk((R)0, (R)0);
+            } else {
+                stage_link<S, R, REC, E, SL>(a, slot, site, xc, yc, zc, tc, dst);
+            }
+        }
+    } else {
+        for (int idx = (int)threadIdx.x; idx < 8 * SL; idx += (int)blockDim.x) {
+            const int slot = idx / SL, ss = idx - slot * SL;
+            const int s = site_in_block(g, a.order, a.xcd_remap, a.cols, ss, SL);
+            cx<R> *dst = lk + slot * E * SL + ss;
+            if (s >= g.V) {
+#pragma unroll
+                for (int k = 0; k < E; ++k) dst[k * SL] = cmk((R)0, (R)0);
+                continue;
+            }
+            int x2, y2, z2, t2;
+            site_coords(g, s, x2, y2, z2, t2);
+            stage_link<S, R, REC, E, SL>(a, slot, s, x2, y2, z2, t2, dst);
+        }
+    }
+    __syncthreads();
+
     if (site >= g.Vp) return;
     const int sub = lane / SL;
     const int j0 = ((blockIdx.y * W + wave) * Q + sub) * NR;
-
-    const LdsLinks<R, REC, SL> lf{lk, sl};
-    dslash_body<S, NR, Q, HW, EPI>(a, site, j0, lf);
+    const LdsLinks<R, E, REC && E == 6, SL> lf{lk, sl};
+    dslash_body_at<S, NR, Q, HW, EPI>(a, site, xc, yc, zc, tc, j0, lf);
 }
 
 // ---------------------------------------------------------------------------
@@ -787,7 +854,8 @@ static hipError_t launch_lds(const DsArgs<S> &a, bool hw, bool epi, hipStream_t 
     using R = typename StoreT<S>::real;
     constexpr int SL = 64 / Q;
     const int W = a.wshare;
-    const size_t need = (size_t)8 * (a.recon ? 6 : 9) * SL * sizeof(cx<R>);
+    const int E = a.recon ? lds_link_components<R, true>() : lds_link_components<R, false>();
+    const size_t need = (size_t)8 * E * SL * sizeof(cx<R>);
     const size_t capr = a.blocks_per_cu > 0 ? (size_t)(160 * 1024) / (size_t)a.blocks_per_cu - 256 : 0;
     const size_t lds = need > capr ? need : capr;
     int nbx = (a.g.Vp + SL - 1) / SL;
