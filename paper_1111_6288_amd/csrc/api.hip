@@ -25,11 +25,22 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "dense.h"
 #include "ov.h"
 #include "ov_internal.h"
 
 using namespace ov;
+
+// A roctx range around every entry point that launches work, so a profiler
+// timeline (rocprofv3 --marker-trace) shows which API call issued each kernel;
+// without a profiler attached the calls return at once.
+struct OvRange {
+    explicit OvRange(const char *name) { roctxRangePushA(name); }
+    ~OvRange() { roctxRangePop(); }
+};
+#define OV_RANGE(name) OvRange ov_range_guard_(name)
 
 // Fixed device scratch of ov_dslash_noalloc (see scratch_init below).
 constexpr size_t kScratchBytes = 64ul << 20;
@@ -1129,6 +1140,7 @@ int ov_memory_used(const ov_ctx *c, int64_t *bytes)
 
 int ov_upload_gauge(ov_ctx *c, const void *U_dev)
 {
+    OV_RANGE("ov_upload_gauge");
     CHK(check_ctx(c));
     if (!U_dev) return fail(c, OV_EINVAL, "null gauge pointer");
     int bad = 0;
@@ -1236,6 +1248,7 @@ int ov_set_sign_params(ov_ctx *c, int n, double eps, double norm, const double *
 
 int ov_upload_eigvecs(ov_ctx *c, int field, int l, const void *V_dev, const double *lambda)
 {
+    OV_RANGE("ov_upload_eigvecs");
     CHK(check_ctx(c));
     if (field < 0 || field >= c->nfield) return fail(c, OV_EINVAL, "field %d outside [0, %d)", field, c->nfield);
     if (l < 0 || l > 256) return fail(c, OV_EINVAL, "small-space dimension %d outside [0, 256]", l);
@@ -1293,6 +1306,7 @@ int ov_upload_eigvecs(ov_ctx *c, int field, int l, const void *V_dev, const doub
 
 int ov_dslash(ov_ctx *c, int prec, int op, int nrhs, const int *field_of_rhs, const void *x, void *y)
 {
+    OV_RANGE("ov_dslash");
     CHK(check_ctx(c));
     CHK(check_prec(c, prec));
     if (op != OV_OP_DW && op != OV_OP_HW) return fail(c, OV_EINVAL, "unknown operator %d", op);
@@ -1307,6 +1321,7 @@ int ov_dslash(ov_ctx *c, int prec, int op, int nrhs, const int *field_of_rhs, co
 
 int ov_dslash_noalloc(ov_ctx *c, int prec, int op, int nrhs, const int *field_of_rhs, const void *x, void *y)
 {
+    OV_RANGE("ov_dslash_noalloc");
     CHK(check_ctx(c));
     CHK(check_prec(c, prec));
     if (op != OV_OP_DW && op != OV_OP_HW) return fail(c, OV_EINVAL, "unknown operator %d", op);
@@ -1348,6 +1363,7 @@ int ov_get_sign_norm(ov_ctx *c, int prec, double *norm)
 
 int ov_sign_apply(ov_ctx *c, int prec, int nrhs, const int *field_of_rhs, const void *x, void *y)
 {
+    OV_RANGE("ov_sign_apply");
     CHK(check_ctx(c));
     CHK(check_prec(c, prec));
     if (!x || !y) return fail(c, OV_EINVAL, "null spinor pointer");
@@ -1363,6 +1379,7 @@ int ov_sign_apply(ov_ctx *c, int prec, int nrhs, const int *field_of_rhs, const 
 int ov_dov_apply(ov_ctx *c, int prec, int nrhs, const int *field_of_rhs, const double *mass, int dagger,
                  const void *x, void *y)
 {
+    OV_RANGE("ov_dov_apply");
     CHK(check_ctx(c));
     CHK(check_prec(c, prec));
     if (!x || !y || !mass) return fail(c, OV_EINVAL, "null pointer argument");
@@ -2021,6 +2038,7 @@ extern "C" {
 int ov_deflated_cg(ov_ctx *c, int nrhs, const int *field_of_rhs, const double *mass, const void *b_dev,
                    void *x_dev, const ov_cg_opts *opts, ov_cg_rhs_report *report)
 {
+    OV_RANGE("ov_deflated_cg");
     CHK(check_ctx(c));
     if (!b_dev || !x_dev || !mass || !opts) return fail(c, OV_EINVAL, "null pointer argument");
     if (!c->have_gauge) return fail(c, OV_ESTATE, "no gauge field uploaded");
@@ -2043,6 +2061,7 @@ int ov_deflated_cg(ov_ctx *c, int nrhs, const int *field_of_rhs, const double *m
 
 int ov_upload_deflation(ov_ctx *c, int field, int k, const void *W_dev)
 {
+    OV_RANGE("ov_upload_deflation");
     CHK(check_ctx(c));
     if (field < 0 || field >= c->nfield) return fail(c, OV_EINVAL, "field %d outside [0, %d)", field, c->nfield);
     if (k < 0 || k > 256) return fail(c, OV_EINVAL, "deflation dimension %d outside [0, 256]", k);
@@ -2104,6 +2123,7 @@ int ov_upload_deflation(ov_ctx *c, int field, int k, const void *W_dev)
 int ov_sign_backward(ov_ctx *c, int field, const void *x_dev, const void *g_dev, void *gU_dev, double *geta,
                      void *gx_dev, int ckpt_every)
 {
+    OV_RANGE("ov_sign_backward");
     CHK(check_ctx(c));
     if (field < 0 || field >= c->nfield) return fail(c, OV_EINVAL, "field %d outside [0, %d)", field, c->nfield);
     if (!x_dev || !g_dev) return fail(c, OV_EINVAL, "null x or g");
@@ -2116,6 +2136,7 @@ int ov_sign_backward(ov_ctx *c, int field, const void *x_dev, const void *g_dev,
 
 int ov_autotune(ov_ctx *c, int prec, int nrhs, const char *cache_path)
 {
+    OV_RANGE("ov_autotune");
     CHK(check_ctx(c));
     CHK(check_prec(c, prec));
     if (!c->have_gauge || c->nfield == 0) return fail(c, OV_ESTATE, "upload the gauge field and fields first");
@@ -2560,6 +2581,7 @@ extern "C" {
 int ov_hw_eigensolve(ov_ctx *c, int field, const ov_eig_opts *o, const void *X0_dev, void *V_dev, double *lambda,
                      double *resid, int install, ov_eig_report *report)
 {
+    OV_RANGE("ov_hw_eigensolve");
     CHK(check_ctx(c));
     if (!o || !X0_dev || !lambda) return fail(c, OV_EINVAL, "null options, start block or lambda");
     if (field < 0 || field >= c->nfield) return fail(c, OV_EINVAL, "field %d outside [0, %d)", field, c->nfield);
@@ -2879,6 +2901,7 @@ extern "C" {
 int ov_multishift_cg(ov_ctx *c, int nrhs, const int *field_of_rhs, int nmass, const double *mass, const void *b_dev,
                      void *x_dev, const ov_mscg_opts *o, ov_mscg_report *report, double *relres)
 {
+    OV_RANGE("ov_multishift_cg");
     CHK(check_ctx(c));
     if (!o || !mass || !b_dev || !x_dev) return fail(c, OV_EINVAL, "null argument");
     if (!c->have_gauge) return fail(c, OV_ESTATE, "no gauge field uploaded");
@@ -3092,6 +3115,7 @@ extern "C" {
 int ov_dov_eigensolve(ov_ctx *c, int field, int chirality, const ov_eig_opts *o, const void *X0_dev, void *W_dev,
                       double *lambda, double *resid, int install, ov_eig_report *report)
 {
+    OV_RANGE("ov_dov_eigensolve");
     CHK(check_ctx(c));
     if (!o || !X0_dev || !lambda) return fail(c, OV_EINVAL, "null options, start block or lambda");
     if (install && !W_dev) return fail(c, OV_EINVAL, "install needs the output basis W_dev");
@@ -3119,6 +3143,7 @@ extern "C" {
 
 int ov_timeslice_norm2(ov_ctx *c, int nrhs, const void *x_dev, double *out)
 {
+    OV_RANGE("ov_timeslice_norm2");
     CHK(check_ctx(c));
     if (nrhs < 0 || nrhs > 65535) return fail(c, OV_EINVAL, "nrhs outside [0, 65535]");
     if (nrhs == 0) return OV_OK;
@@ -3137,6 +3162,7 @@ int ov_timeslice_norm2(ov_ctx *c, int nrhs, const void *x_dev, double *out)
 
 int ov_pion_correlator(ov_ctx *c, int nsrc, const void *S_dev, double *G)
 {
+    OV_RANGE("ov_pion_correlator");
     CHK(check_ctx(c));
     if (nsrc < 1 || nsrc > 65535) return fail(c, OV_EINVAL, "nsrc outside [1, 65535]");
     if (!S_dev || !G) return fail(c, OV_EINVAL, "null argument");
@@ -3176,6 +3202,7 @@ extern "C" {
 int ov_correlator_deta(ov_ctx *c, int field, double mass, int nsrc, const void *b_dev, const double *w,
                        double *C, double *dF, const ov_cg_opts *opts)
 {
+    OV_RANGE("ov_correlator_deta");
     CHK(check_ctx(c));
     if (field < 0 || field >= c->nfield) return fail(c, OV_EINVAL, "field %d outside [0, %d)", field, c->nfield);
     if (nsrc < 1 || nsrc > 4096) return fail(c, OV_EINVAL, "nsrc outside [1, 4096]");
