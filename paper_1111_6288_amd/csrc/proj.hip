@@ -26,7 +26,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // j + 16k, and D[i][j] lands in lane j + 16 (i mod 4), register i div 4; so
 // lane q, register r holds row 4r + q/16, column q%16.
 //
-// Workgroup (c, y) = W waves (W = blockDim / 64) owns K-chunk c and the
+// Workgroup (y, c) = W waves (W = blockDim / 64) owns K-chunk c and the
 // vector tiles y W MT + w + W m (m < MT) of its waves w, with all RHS tiles
 // (up to NT).  The launcher takes W = 4 and MT = 2: at about 160 VGPRs three
 // waves fit per SIMD, so three such workgroups share a CU, where one
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict
     const int W = blockDim.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const long K = 12L * Vp, half = 6L * Vp;
-    const long k0 = (long)blockIdx.x * chunk;
+    const long k0 = (long)blockIdx.y * chunk;
     const long k1 = (k0 + chunk < K) ? k0 + chunk : K;
 
     v4d cre[MT][NT], cim[MT][NT];
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict
     // per-lane row pointers
     const double2 *vp[MT];
     bool vok[MT];
-    const int tile0 = blockIdx.y * W * MT + wave;
+    const int tile0 = blockIdx.x * W * MT + wave;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         const int i = (tile0 + W * m) * 16 + row;
@@ -127,7 +127,124 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict
     }
 
     // partial[chunk][j][i]
-    double2 *pc = part + (long)blockIdx.x * n * l;
+    double2 *pc = part + (long)blockIdx.y * n * l;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = (tile0 + W * m) * 16 + 4 * r + kq;
+                const int j = t * 16 + row;
+                if (i < l && j < n) pc[(long)j * l + i] = make_double2(cre[m][t][r], cim[m][t][r]);
+            }
+}
+
+// The same contraction for X in the paired FP32 layout, where one 16-byte
+// element holds the site's components 2p and 2p+1.  Walking k plane by plane
+// would use half of every X line (the partner plane is reached a plane
+// later, long after the line left L1); here each step covers four sites of
+// both planes of a pair: one 16-byte X load per lane feeds the MFMA steps of
+// plane 2p and of plane 2p+1.  K-chunks count pairs of planes (chunk sites of
+// the 6 Vp pair positions).
+template <int MT, int NT>
+__global__ __launch_bounds__(512) void k_proj_dot_mfma_pair(const double2 *__restrict__ V, int l, long vstride,
+                                                            const float2 *__restrict__ X, long xstride,
+                                                            const int *slots, int n, int Vp, int g5x, long chunk,
+                                                            double2 *__restrict__ part)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int W = blockDim.x >> 6;
+    const int row = lane & 15, kq = lane >> 4;
+    const long K2 = 6L * Vp;
+    const long k0 = (long)blockIdx.y * chunk;
+    const long k1 = (k0 + chunk < K2) ? k0 + chunk : K2;
+
+    v4d cre[MT][NT], cim[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            cre[m][t] = (v4d){0, 0, 0, 0};
+            cim[m][t] = (v4d){0, 0, 0, 0};
+        }
+    const double2 *vp[MT];
+    bool vok[MT];
+    const int tile0 = blockIdx.x * W * MT + wave;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const int i = (tile0 + W * m) * 16 + row;
+        vok[m] = i < l;
+        vp[m] = V + (long)(vok[m] ? i : 0) * vstride;
+    }
+    const float2 *xp[NT];
+    bool xok[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int j = t * 16 + row;
+        xok[t] = j < n;
+        const int s = xok[t] ? (slots ? slots[j] : j) : 0;
+        xp[t] = X + (long)s * xstride;
+    }
+    // (pair-plane, site) of kb; Vp and kb are multiples of 4
+    long pp = k0 / Vp, st = k0 - pp * Vp;
+    double2 vn0[MT], vn1[MT];
+    cx<double> xa[NT], xb[NT];
+    auto load_step = [&](long kb) {
+        const bool kin = kb + kq < k1;
+        const long site = st + kq;
+        const double sg = (g5x && pp >= 3) ? -1.0 : 1.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (kin && xok[t]) v = *(const float4 *)(xp[t] + 2 * (pp * (long)Vp + site));
+            xa[t] = {sg * (double)v.x, sg * (double)v.y};
+            xb[t] = {sg * (double)v.z, sg * (double)v.w};
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const bool ok = kin && vok[m];
+            vn0[m] = ok ? vp[m][(2 * pp) * Vp + site] : make_double2(0.0, 0.0);
+            vn1[m] = ok ? vp[m][(2 * pp + 1) * Vp + site] : make_double2(0.0, 0.0);
+        }
+        st += 4;
+        if (st >= Vp) {
+            st -= Vp;
+            ++pp;
+        }
+    };
+    auto mfma_plane = [&](const double2 (&vc)[MT], const cx<double> (&xc)[NT]) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const double2 v = vc[m];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                cre[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, xc[t].x, cre[m][t], 0, 0, 0);
+                cre[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.y, xc[t].y, cre[m][t], 0, 0, 0);
+                cim[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, xc[t].y, cim[m][t], 0, 0, 0);
+                cim[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-v.y, xc[t].x, cim[m][t], 0, 0, 0);
+            }
+        }
+    };
+    if (k0 < k1) load_step(k0);
+    for (long kb = k0; kb < k1; kb += 4) {
+        double2 v0[MT], v1[MT];
+        cx<double> x0[NT], x1[NT];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            v0[m] = vn0[m];
+            v1[m] = vn1[m];
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            x0[t] = xa[t];
+            x1[t] = xb[t];
+        }
+        if (kb + 4 < k1) load_step(kb + 4);
+        mfma_plane(v0, x0);
+        mfma_plane(v1, x1);
+    }
+    double2 *pc = part + (long)blockIdx.y * n * l;
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -183,9 +300,15 @@ __global__ __launch_bounds__(256) void k_proj_expand_mfma(const double2 *__restr
         dre[t] = (v4d){0, 0, 0, 0};
         dim[t] = (v4d){0, 0, 0, 0};
     }
+    // V of step ib + 4 is requested before the matrix-core work of step ib
+    double2 vn = (iq < l && kok) ? V[(long)iq * vstride + kk] : make_double2(0.0, 0.0);
     for (int ib = 0; ib < l; ib += 4) {
         const int i = ib + iq;
-        double2 v = (i < l && kok) ? V[(long)i * vstride + kk] : make_double2(0.0, 0.0);
+        const double2 v = vn;
+        if (ib + 4 < l) {
+            const int i2 = i + 4;
+            vn = (i2 < l && kok) ? V[(long)i2 * vstride + kk] : make_double2(0.0, 0.0);
+        }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int j = t * 16 + col;    // A row held by this lane: j = q%16, i = q/16
@@ -251,7 +374,19 @@ static void launch_dot_mt(const double2 *V, int l, long vstride, const S *X, lon
 {
     const int tiles = (l + 15) / 16;
     const int ny = (tiles + waves * MT - 1) / (waves * MT);
-    hipLaunchKernelGGL((k_proj_dot_mfma<S, MT, NT>), dim3(nchunk, ny), dim3(64 * waves), 0, st, V, l, vstride, X,
+    // the ny workgroups of a K-chunk are consecutive in dispatch order, so they
+    // run at the same time and the second one reads the chunk of X from L2
+    hipLaunchKernelGGL((k_proj_dot_mfma<S, MT, NT>), dim3(ny, nchunk), dim3(64 * waves), 0, st, V, l, vstride, X,
+                       xstride, slots, n, Vp, g5x, chunk, part);
+}
+
+template <int MT, int NT>
+static void launch_dot_pair(const double2 *V, int l, long vstride, const float2 *X, long xstride, const int *slots,
+                            int n, int Vp, int g5x, long chunk, int nchunk, double2 *part, int waves, hipStream_t st)
+{
+    const int tiles = (l + 15) / 16;
+    const int ny = (tiles + waves * MT - 1) / (waves * MT);
+    hipLaunchKernelGGL((k_proj_dot_mfma_pair<MT, NT>), dim3(ny, nchunk), dim3(64 * waves), 0, st, V, l, vstride, X,
                        xstride, slots, n, Vp, g5x, chunk, part);
 }
 
@@ -262,21 +397,37 @@ hipError_t launch_proj_dot(const double2 *V, int l, long vstride, const S *X, lo
     if (l <= 0 || n <= 0) return hipSuccess;
     if (n > 48 || l > 256) return hipErrorInvalidValue;   // caller splits larger batches
     const long K = 12L * Vp;
-    const long chunk = proj_dot_chunk(K);
-    const int nchunk = (int)((K + chunk - 1) / chunk);
+    long chunk = proj_dot_chunk(K);
+    int nchunk = (int)((K + chunk - 1) / chunk);
+    if constexpr (Pair<S>::E == 2) {
+        // chunks of pair positions: half as many positions per chunk (rounded up
+        // to a multiple of 4), so at most as many chunks as the partial buffer holds
+        chunk = ((chunk / 2) + 3) & ~3L;
+        nchunk = (int)((6L * Vp + chunk - 1) / chunk);
+    }
     // two vector tiles per wave, up to four waves per workgroup, the
     // remaining tiles in further workgroups along y
     const int tiles = (l + 15) / 16;
     const int mt = tiles >= 2 ? 2 : 1;
     const int waves = std::min(4, (tiles + mt - 1) / mt);
     const int nt = (n + 15) / 16;
+    if constexpr (Pair<S>::E == 2) {
+#define OV_DOT_CASE(M, N) \
+    if (mt == M && nt == N) \
+    launch_dot_pair<M, N>(V, l, vstride, X, xstride, slots, n, Vp, g5x, chunk, nchunk, part, waves, st)
+        OV_DOT_CASE(1, 1); else OV_DOT_CASE(1, 2); else OV_DOT_CASE(1, 3);
+        else OV_DOT_CASE(2, 1); else OV_DOT_CASE(2, 2); else OV_DOT_CASE(2, 3);
+        else return hipErrorInvalidValue;
+#undef OV_DOT_CASE
+    } else {
 #define OV_DOT_CASE(M, N) \
     if (mt == M && nt == N) \
     launch_dot_mt<S, M, N>(V, l, vstride, X, xstride, slots, n, Vp, g5x, chunk, nchunk, part, waves, st)
-    OV_DOT_CASE(1, 1); else OV_DOT_CASE(1, 2); else OV_DOT_CASE(1, 3);
-    else OV_DOT_CASE(2, 1); else OV_DOT_CASE(2, 2); else OV_DOT_CASE(2, 3);
-    else return hipErrorInvalidValue;
+        OV_DOT_CASE(1, 1); else OV_DOT_CASE(1, 2); else OV_DOT_CASE(1, 3);
+        else OV_DOT_CASE(2, 1); else OV_DOT_CASE(2, 2); else OV_DOT_CASE(2, 3);
+        else return hipErrorInvalidValue;
 #undef OV_DOT_CASE
+    }
     const int nl = n * l;
     hipLaunchKernelGGL(k_proj_reduce, dim3((nl + 255) / 256), dim3(256), 0, st, part, nchunk, nl, C);
     return hipGetLastError();
@@ -292,6 +443,17 @@ hipError_t launch_proj_expand(const double2 *V, int l, long vstride, const SX *X
     const long K = 12L * Vp;
     const int nblk = (int)((K + 63) / 64);
     const int nt = (n + 15) / 16;
+    if (nt == 1)
+            hipLaunchKernelGGL((k_proj_expand_mfma_pair<1>), dim3(nb2), dim3(256), 0, st, V, l, vstride, X, xstride,
+                               alpha, Y, ystride, slots, n, Vp, E, beta);
+        else if (nt == 2)
+            hipLaunchKernelGGL((k_proj_expand_mfma_pair<2>), dim3(nb2), dim3(256), 0, st, V, l, vstride, X, xstride,
+                               alpha, Y, ystride, slots, n, Vp, E, beta);
+        else
+            hipLaunchKernelGGL((k_proj_expand_mfma_pair<3>), dim3(nb2), dim3(256), 0, st, V, l, vstride, X, xstride,
+                               alpha, Y, ystride, slots, n, Vp, E, beta);
+        return hipGetLastError();
+    }
     if (nt == 1)
         hipLaunchKernelGGL((k_proj_expand_mfma<SX, SY, 1>), dim3(nblk), dim3(256), 0, st, V, l, vstride, X, xstride,
                            alpha, Y, ystride, slots, n, Vp, E, beta);
