@@ -444,17 +444,6 @@ hipError_t launch_proj_expand(const double2 *V, int l, long vstride, const SX *X
     const int nblk = (int)((K + 63) / 64);
     const int nt = (n + 15) / 16;
     if (nt == 1)
-            hipLaunchKernelGGL((k_proj_expand_mfma_pair<1>), dim3(nb2), dim3(256), 0, st, V, l, vstride, X, xstride,
-                               alpha, Y, ystride, slots, n, Vp, E, beta);
-        else if (nt == 2)
-            hipLaunchKernelGGL((k_proj_expand_mfma_pair<2>), dim3(nb2), dim3(256), 0, st, V, l, vstride, X, xstride,
-                               alpha, Y, ystride, slots, n, Vp, E, beta);
-        else
-            hipLaunchKernelGGL((k_proj_expand_mfma_pair<3>), dim3(nb2), dim3(256), 0, st, V, l, vstride, X, xstride,
-                               alpha, Y, ystride, slots, n, Vp, E, beta);
-        return hipGetLastError();
-    }
-    if (nt == 1)
         hipLaunchKernelGGL((k_proj_expand_mfma<SX, SY, 1>), dim3(nblk), dim3(256), 0, st, V, l, vstride, X, xstride,
                            alpha, Y, ystride, slots, n, Vp, E, beta);
     else if (nt == 2)
