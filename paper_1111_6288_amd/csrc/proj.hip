@@ -277,21 +277,25 @@ __global__ void k_proj_reduce(const double2 *__restrict__ part, int nchunk, int 
 // and B[i = q/16][k = q%16]; the result row j = 4r + q/16, column k = q%16,
 // so a store instruction writes four runs of 16 consecutive k.
 // Each wave owns 16 consecutive k (one column block) and NT RHS tiles.
+// The coefficients E are staged through LDS 16 vector indices at a time:
+// the four waves of a workgroup share each slice (one coalesced load per
+// workgroup instead of a 16-row gather per wave and step).
 template <class SX, class SY, int NT>
 __global__ __launch_bounds__(256) void k_proj_expand_mfma(const double2 *__restrict__ V, int l, long vstride,
                                                           const SX *X, long xstride, double alpha,
                                                           SY *Y, long ystride, const int *slots, int n,
                                                           int Vp, const double2 *__restrict__ E, double beta)
 {
+    constexpr int EI = 16, EJ = 16 * NT, EP = EJ + 1;   // slice of E: EI vector indices x EJ RHS (row padded)
+    __shared__ double2 es[EI * EP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, iq = lane >> 4;
     const long K = 12L * Vp;
     const long kbase = ((long)blockIdx.x * 4 + wave) * 16;
-    if (kbase >= K) return;
     const long kk = kbase + col;          // B column handled by this lane
-    const bool kok = kk < K;
+    const bool kok = kk < K;              // waves past the end still take part in the barriers
     // the 16 columns of a wave lie in one plane (Vp is a multiple of 16)
-    const long pl = kbase / Vp, st = kk - pl * Vp;
+    const long pl = kk / Vp, st = kk - pl * Vp;
     const long xk = cpos<SX>((int)pl, st, Vp), yk = cpos<SY>((int)pl, st, Vp);
 
     v4d dre[NT], dim[NT];
@@ -302,22 +306,31 @@ __global__ __launch_bounds__(256) void k_proj_expand_mfma(const double2 *__restr
     }
     // V of step ib + 4 is requested before the matrix-core work of step ib
     double2 vn = (iq < l && kok) ? V[(long)iq * vstride + kk] : make_double2(0.0, 0.0);
-    for (int ib = 0; ib < l; ib += 4) {
-        const int i = ib + iq;
-        const double2 v = vn;
-        if (ib + 4 < l) {
-            const int i2 = i + 4;
-            vn = (i2 < l && kok) ? V[(long)i2 * vstride + kk] : make_double2(0.0, 0.0);
+    for (int i0 = 0; i0 < l; i0 += EI) {
+        __syncthreads();   // the previous slice has been consumed
+        for (int e = (int)threadIdx.x; e < EI * EJ; e += (int)blockDim.x) {
+            const int j = e / EI, ii = e - j * EI;   // ii fastest: contiguous reads of a row of E
+            es[ii * EP + j] = (i0 + ii < l && j < n) ? E[(long)j * l + i0 + ii] : make_double2(0.0, 0.0);
         }
+        __syncthreads();
+        const int iend = (i0 + EI < l) ? i0 + EI : l;
+        for (int ib = i0; ib < iend; ib += 4) {
+            const int i = ib + iq;
+            const double2 v = vn;
+            if (ib + 4 < l) {
+                const int i2 = i + 4;
+                vn = (i2 < l && kok) ? V[(long)i2 * vstride + kk] : make_double2(0.0, 0.0);
+            }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int j = t * 16 + col;    // A row held by this lane: j = q%16, i = q/16
-            double2 e = (i < l && j < n) ? E[(long)j * l + i] : make_double2(0.0, 0.0);
-            // (e * v): Re = er vr - ei vi ; Im = er vi + ei vr
-            dre[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.x, v.x, dre[t], 0, 0, 0);
-            dre[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-e.y, v.y, dre[t], 0, 0, 0);
-            dim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.x, v.y, dim[t], 0, 0, 0);
-            dim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.y, v.x, dim[t], 0, 0, 0);
+            for (int t = 0; t < NT; ++t) {
+                // A row held by this lane: j = q%16, i = q/16 (zero beyond l and n: the slice is padded)
+                const double2 e = es[(ib - i0 + iq) * EP + t * 16 + col];
+                // (e * v): Re = er vr - ei vi ; Im = er vi + ei vr
+                dre[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.x, v.x, dre[t], 0, 0, 0);
+                dre[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-e.y, v.y, dre[t], 0, 0, 0);
+                dim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.x, v.y, dim[t], 0, 0, 0);
+                dim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.y, v.x, dim[t], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
