@@ -153,6 +153,12 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma_pair(const double2 *__res
                                                             const int *slots, int n, int Vp, int g5x, long chunk,
                                                             double2 *__restrict__ part)
 {
+    // X is staged through LDS 16 sites at a time (all waves of the workgroup
+    // read the same X; one coalesced load per workgroup instead of a 16-row
+    // gather per wave and step).  chunk and Vp are multiples of 16, so a
+    // 16-site slice never crosses a pair-plane.
+    constexpr int XS = 16, XJ = 16 * NT, XP = XJ + 1;
+    __shared__ float4 xs[XS * XP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int W = blockDim.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
@@ -177,30 +183,12 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma_pair(const double2 *__res
         vok[m] = i < l;
         vp[m] = V + (long)(vok[m] ? i : 0) * vstride;
     }
-    const float2 *xp[NT];
-    bool xok[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int j = t * 16 + row;
-        xok[t] = j < n;
-        const int s = xok[t] ? (slots ? slots[j] : j) : 0;
-        xp[t] = X + (long)s * xstride;
-    }
     // (pair-plane, site) of kb; Vp and kb are multiples of 4
     long pp = k0 / Vp, st = k0 - pp * Vp;
     double2 vn0[MT], vn1[MT];
-    cx<double> xa[NT], xb[NT];
-    auto load_step = [&](long kb) {
+    auto load_v = [&](long kb) {
         const bool kin = kb + kq < k1;
         const long site = st + kq;
-        const double sg = (g5x && pp >= 3) ? -1.0 : 1.0;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (kin && xok[t]) v = *(const float4 *)(xp[t] + 2 * (pp * (long)Vp + site));
-            xa[t] = {sg * (double)v.x, sg * (double)v.y};
-            xb[t] = {sg * (double)v.z, sg * (double)v.w};
-        }
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             const bool ok = kin && vok[m];
@@ -226,23 +214,42 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma_pair(const double2 *__res
             }
         }
     };
-    if (k0 < k1) load_step(k0);
-    for (long kb = k0; kb < k1; kb += 4) {
-        double2 v0[MT], v1[MT];
-        cx<double> x0[NT], x1[NT];
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            v0[m] = vn0[m];
-            v1[m] = vn1[m];
+    if (k0 < k1) load_v(k0);
+    for (long s0 = k0; s0 < k1; s0 += XS) {
+        __syncthreads();   // the previous slice has been consumed
+        {
+            const long spp = s0 / Vp, sst = s0 - spp * Vp;
+            for (int e = (int)threadIdx.x; e < XS * XJ; e += (int)blockDim.x) {
+                const int j = e / XS, ii = e - j * XS;   // sites fastest: contiguous reads of one RHS
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (j < n && s0 + ii < k1) {
+                    const int sj = slots ? slots[j] : j;
+                    v = *(const float4 *)(X + (long)sj * xstride + 2 * (spp * (long)Vp + sst + ii));
+                }
+                xs[ii * XP + j] = v;
+            }
         }
+        __syncthreads();
+        const double sg = (g5x && s0 >= 3L * Vp) ? -1.0 : 1.0;
+        const long send = (s0 + XS < k1) ? s0 + XS : k1;
+        for (long kb = s0; kb < send; kb += 4) {
+            double2 v0[MT], v1[MT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            x0[t] = xa[t];
-            x1[t] = xb[t];
+            for (int m = 0; m < MT; ++m) {
+                v0[m] = vn0[m];
+                v1[m] = vn1[m];
+            }
+            if (kb + 4 < k1) load_v(kb + 4);
+            cx<double> x0[NT], x1[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const float4 v = xs[(int)(kb - s0 + kq) * XP + t * 16 + row];
+                x0[t] = {sg * (double)v.x, sg * (double)v.y};
+                x1[t] = {sg * (double)v.z, sg * (double)v.w};
+            }
+            mfma_plane(v0, x0);
+            mfma_plane(v1, x1);
         }
-        if (kb + 4 < k1) load_step(kb + 4);
-        mfma_plane(v0, x0);
-        mfma_plane(v1, x1);
     }
     double2 *pc = part + (long)blockIdx.y * n * l;
 #pragma unroll
@@ -414,8 +421,8 @@ hipError_t launch_proj_dot(const double2 *V, int l, long vstride, const S *X, lo
     int nchunk = (int)((K + chunk - 1) / chunk);
     if constexpr (Pair<S>::E == 2) {
         // chunks of pair positions: half as many positions per chunk (rounded up
-        // to a multiple of 4), so at most as many chunks as the partial buffer holds
-        chunk = ((chunk / 2) + 3) & ~3L;
+        // to a multiple of 16), so at most as many chunks as the partial buffer holds
+        chunk = ((chunk / 2) + 15) & ~15L;
         nchunk = (int)((6L * Vp + chunk - 1) / chunk);
     }
     // two vector tiles per wave, up to four waves per workgroup, the
