@@ -39,6 +39,12 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict
                                                        const int *slots, int n, int Vp, int g5x, long chunk,
                                                        double2 *__restrict__ part)
 {
+    // X is staged through LDS 16 k at a time (all waves of the workgroup read
+    // the same X; one coalesced load per workgroup instead of a 16-row gather
+    // per wave and step).  chunk and Vp are multiples of 16, so a slice lies in
+    // one plane.
+    constexpr int XS = 16, XJ = 16 * NT, XP = XJ + 1;
+    __shared__ double2 xs[XS * XP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int W = blockDim.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
@@ -65,63 +71,55 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict
         vok[m] = i < l;
         vp[m] = V + (long)(vok[m] ? i : 0) * vstride;
     }
-    const S *xp[NT];
-    bool xok[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int j = t * 16 + row;
-        xok[t] = j < n;
-        const int s = xok[t] ? (slots ? slots[j] : j) : 0;
-        xp[t] = X + (long)s * xstride;
-    }
-
-    // (plane, site) of kb, advanced with it: kb and Vp are multiples of 4, so
-    // kb + kq stays in the plane of kb
-    long pl = k0 / Vp, st = k0 - pl * Vp;
-    // The loads of step kb + 4 are issued before the matrix-core work of step
-    // kb (one wave per SIMD fits, so nothing else would hide their latency).
+    // V of step kb + 4 is requested before the matrix-core work of step kb
     double2 vn[MT];
-    cx<double> xn[NT];
-    auto load_step = [&](long kb) {
+    auto load_v = [&](long kb) {
         const long k = kb + kq;
         const bool kin = k < k1;
-        const long xk = cpos<S>((int)pl, st + kq, Vp);
-        st += 4;
-        if (st >= Vp) {
-            st -= Vp;
-            ++pl;
-        }
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            cx<double> x = (kin && xok[t]) ? ldc<double>(xp[t], xk) : cx<double>{0.0, 0.0};
-            if (g5x && k >= half) x = {-x.x, -x.y};
-            xn[t] = x;
-        }
 #pragma unroll
         for (int m = 0; m < MT; ++m) vn[m] = (kin && vok[m]) ? vp[m][k] : make_double2(0.0, 0.0);
     };
-    if (k0 < k1) load_step(k0);
-    for (long kb = k0; kb < k1; kb += 4) {
-        double2 vc[MT];
-        double xr[NT], xi[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            xr[t] = xn[t].x;
-            xi[t] = xn[t].y;
+    if (k0 < k1) load_v(k0);
+    for (long s0 = k0; s0 < k1; s0 += XS) {
+        __syncthreads();   // the previous slice has been consumed
+        {
+            const long pl = s0 / Vp, sst = s0 - pl * Vp;
+            for (int e = (int)threadIdx.x; e < XS * XJ; e += (int)blockDim.x) {
+                const int j = e / XS, ii = e - j * XS;   // k fastest: contiguous reads of one RHS
+                cx<double> x = {0.0, 0.0};
+                if (j < n && s0 + ii < k1) {
+                    const int sj = slots ? slots[j] : j;
+                    x = ldc<double>(X + (long)sj * xstride, cpos<S>((int)pl, sst + ii, Vp));
+                }
+                xs[ii * XP + j] = make_double2(x.x, x.y);
+            }
         }
+        __syncthreads();
+        const double sg = (g5x && s0 >= half) ? -1.0 : 1.0;
+        const long send = (s0 + XS < k1) ? s0 + XS : k1;
+        for (long kb = s0; kb < send; kb += 4) {
+            double2 vc[MT];
 #pragma unroll
-        for (int m = 0; m < MT; ++m) vc[m] = vn[m];
-        if (kb + 4 < k1) load_step(kb + 4);
-#pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            const double2 v = vc[m];
+            for (int m = 0; m < MT; ++m) vc[m] = vn[m];
+            if (kb + 4 < k1) load_v(kb + 4);
+            double xr[NT], xi[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                // Re: vr xr + vi xi ; Im: vr xi - vi xr
-                cre[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, xr[t], cre[m][t], 0, 0, 0);
-                cre[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.y, xi[t], cre[m][t], 0, 0, 0);
-                cim[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, xi[t], cim[m][t], 0, 0, 0);
-                cim[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-v.y, xr[t], cim[m][t], 0, 0, 0);
+                const double2 x = xs[(int)(kb - s0 + kq) * XP + t * 16 + row];
+                xr[t] = sg * x.x;
+                xi[t] = sg * x.y;
+            }
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const double2 v = vc[m];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    // Re: vr xr + vi xi ; Im: vr xi - vi xr
+                    cre[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, xr[t], cre[m][t], 0, 0, 0);
+                    cre[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.y, xi[t], cre[m][t], 0, 0, 0);
+                    cim[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, xi[t], cim[m][t], 0, 0, 0);
+                    cim[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-v.y, xr[t], cim[m][t], 0, 0, 0);
+                }
             }
         }
     }
@@ -380,10 +378,10 @@ __global__ void k_mul_coef(const double2 *C, const double *w, int l, int n, doub
 // ------------------------------------------------------------------ launchers
 long proj_dot_chunk(long K)
 {
-    // split K into about 1024 chunks (each a multiple of 4); with the tile split
+    // split K into about 1024 chunks (each a multiple of 16); with the tile split
     // along y that is 2048 workgroups for l = 200
     long c = (K + 1023) / 1024;
-    c = (c + 3) & ~3L;
+    c = (c + 15) & ~15L;   // a multiple of 16: the kernels stage X 16 positions at a time
     if (c < 64) c = 64;
     return c;
 }
