@@ -45,7 +45,7 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict
     // one plane.
     constexpr int XS = 16, XJ = 16 * NT, XP = XJ + 1;
     __shared__ double2 xs[XS * XP];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int W = blockDim.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const long K = 12L * Vp, half = 6L * Vp;
@@ -63,11 +63,12 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict
 
     // per-lane row pointers
     const double2 *vp[MT];
-    bool vok[MT];
+    bool vok[MT], tv[MT];
     const int tile0 = blockIdx.x * W * MT + wave;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         const int i = (tile0 + W * m) * 16 + row;
+        tv[m] = (tile0 + W * m) * 16 < l;   // wave-uniform: tiles past l skip their matrix-core work
         vok[m] = i < l;
         vp[m] = V + (long)(vok[m] ? i : 0) * vstride;
     }
@@ -111,6 +112,7 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict
             }
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
+                if (!tv[m]) continue;
                 const double2 v = vc[m];
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma_pair(const double2 *__res
     // 16-site slice never crosses a pair-plane.
     constexpr int XS = 16, XJ = 16 * NT, XP = XJ + 1;
     __shared__ float4 xs[XS * XP];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int W = blockDim.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const long K2 = 6L * Vp;
@@ -173,11 +175,12 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma_pair(const double2 *__res
             cim[m][t] = (v4d){0, 0, 0, 0};
         }
     const double2 *vp[MT];
-    bool vok[MT];
+    bool vok[MT], tv[MT];
     const int tile0 = blockIdx.x * W * MT + wave;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         const int i = (tile0 + W * m) * 16 + row;
+        tv[m] = (tile0 + W * m) * 16 < l;   // wave-uniform: tiles past l skip their matrix-core work
         vok[m] = i < l;
         vp[m] = V + (long)(vok[m] ? i : 0) * vstride;
     }
@@ -202,6 +205,7 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma_pair(const double2 *__res
     auto mfma_plane = [&](const double2 (&vc)[MT], const cx<double> (&xc)[NT]) {
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
+            if (!tv[m]) continue;
             const double2 v = vc[m];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
