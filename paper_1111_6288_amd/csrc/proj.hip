@@ -10,7 +10,7 @@
 // mapped) or BF16; every product and sum is FP64.  The dot runs split-K:
 // each workgroup reduces one K-chunk to a partial l x n block, then a fixed-
 // order pass sums the partials (deterministic).  Both use the matrix cores
-// (v_mfma_f64_16x16x4f64) with 16x16 tiles of (vector, RHS).
+// (v_mfma_f64_4x4x4f64) on tiles of 16 vectors x 4 RHS.
 #include <algorithm>
 
 #include "ov_device.h"
@@ -21,47 +21,55 @@ namespace ov {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // --------------------------------------------------------------- V^dag X (MFMA)
-// Lane layout of v_mfma_f64_16x16x4f64 (D = A B + C, A 16x4, B 4x16), as
-// measured on gfx950: A[i][k] comes from lane i + 16k, B[k][j] from lane
-// j + 16k, and D[i][j] lands in lane j + 16 (i mod 4), register i div 4; so
-// lane q, register r holds row 4r + q/16, column q%16.
+// The matrix-core instruction is v_mfma_f64_4x4x4f64: four independent
+// 4x4x4 products per wavefront.  Its lane layout, as measured on gfx950:
+// block b = (lane >> 2) & 3; A_b[i][k] comes from lane i + 4b + 16k,
+// B_b[k][j] from lane j + 4b + 16k, and D_b[i][j] lands in lane 16i + 4b + j.
+// The four blocks are taken as the four row groups of one 16-row tile: lane
+// q holds A = V[row q%16][k q/16], B = X[k q/16][column 4jb + q%4] (the same
+// value in all four blocks) and receives C[row 4((q>>2)&3) + q/16][column
+// 4jb + q%4].  Four such instructions do the work of one 16x16x4 step, but on
+// gfx950 they sustain ~72 TFLOP/s of FP64 against ~47 for v_mfma_f64_16x16x4f64
+// (register-only loops of independent instructions), and RHS columns come in
+// groups of 4, so a batch of 36 RHS wastes nothing where 16-wide tiles pad it
+// to 48.
 //
 // Workgroup (y, c) = W waves (W = blockDim / 64) owns K-chunk c and the
-// vector tiles y W MT + w + W m (m < MT) of its waves w, with all RHS tiles
-// (up to NT).  The launcher takes W = 4 and MT = 2: at about 160 VGPRs three
-// waves fit per SIMD, so three such workgroups share a CU, where one
-// workgroup holding all 13 tiles of l = 200 (7 waves) would leave it at 7
-// waves.  Per MFMA step lane q holds A[i = q%16][k = q/16] = V and
-// B[k = q/16][j = q%16] = X.
+// vector tiles y W MT + w + W m (m < MT) of its waves w, with all RHS (up to
+// 16 NT).  The launcher takes W = 4 and MT = 2: three waves fit per SIMD, so
+// three such workgroups share a CU, where one workgroup holding all 13 tiles
+// of l = 200 (7 waves) would leave it at 7 waves.  X is staged through LDS
+// 32 positions at a time, with the g5 sign applied there: all waves of the
+// workgroup read the same X, so one coalesced load per workgroup replaces a
+// 16-row gather per wave and step.  chunk and Vp are multiples of 32, so a
+// slice lies in one plane (one pair-plane for the paired layout) and on one
+// side of the g5 sign change.
+//
+// Row padding of the staged X: rows of XJ + 4 elements put the four k rows a
+// lane group reads at different bank offsets.
 template <class S, int MT, int NT>
-__global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict__ V, int l, long vstride,
+__global__ __launch_bounds__(256, 3) void k_proj_dot_mfma(const double2 *__restrict__ V, int l, long vstride,
                                                        const S *__restrict__ X, long xstride,
                                                        const int *slots, int n, int Vp, int g5x, long chunk,
                                                        double2 *__restrict__ part)
 {
-    // X is staged through LDS 16 k at a time (all waves of the workgroup read
-    // the same X; one coalesced load per workgroup instead of a 16-row gather
-    // per wave and step).  chunk and Vp are multiples of 16, so a slice lies in
-    // one plane.
-    constexpr int XS = 16, XJ = 16 * NT, XP = XJ + 1;
+    constexpr int XS = 32, XJ = 16 * NT, XP = XJ + 4;
     __shared__ double2 xs[XS * XP];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int W = blockDim.x >> 6;
-    const int row = lane & 15, kq = lane >> 4;
+    const int row = lane & 15, kq = lane >> 4, jq = lane & 3;
     const long K = 12L * Vp, half = 6L * Vp;
     const long k0 = (long)blockIdx.y * chunk;
     const long k1 = (k0 + chunk < K) ? k0 + chunk : K;
 
-    v4d cre[MT][NT], cim[MT][NT];
+    double are[MT][NT][4], aim[MT][NT][4];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            cre[m][t] = (v4d){0, 0, 0, 0};
-            cim[m][t] = (v4d){0, 0, 0, 0};
-        }
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) are[m][t][jb] = aim[m][t][jb] = 0.0;
 
-    // per-lane row pointers
     const double2 *vp[MT];
     bool vok[MT], tv[MT];
     const int tile0 = blockIdx.x * W * MT + wave;
@@ -85,6 +93,7 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict
         __syncthreads();   // the previous slice has been consumed
         {
             const long pl = s0 / Vp, sst = s0 - pl * Vp;
+            const double sg = (g5x && s0 >= half) ? -1.0 : 1.0;
             for (int e = (int)threadIdx.x; e < XS * XJ; e += (int)blockDim.x) {
                 const int j = e / XS, ii = e - j * XS;   // k fastest: contiguous reads of one RHS
                 cx<double> x = {0.0, 0.0};
@@ -92,51 +101,49 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict
                     const int sj = slots ? slots[j] : j;
                     x = ldc<double>(X + (long)sj * xstride, cpos<S>((int)pl, sst + ii, Vp));
                 }
-                xs[ii * XP + j] = make_double2(x.x, x.y);
+                xs[ii * XP + j] = make_double2(sg * x.x, sg * x.y);
             }
         }
         __syncthreads();
-        const double sg = (g5x && s0 >= half) ? -1.0 : 1.0;
         const long send = (s0 + XS < k1) ? s0 + XS : k1;
         for (long kb = s0; kb < send; kb += 4) {
             double2 vc[MT];
 #pragma unroll
             for (int m = 0; m < MT; ++m) vc[m] = vn[m];
             if (kb + 4 < k1) load_v(kb + 4);
-            double xr[NT], xi[NT];
+            const double2 *xrow = xs + (int)(kb - s0 + kq) * XP + jq;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const double2 x = xs[(int)(kb - s0 + kq) * XP + t * 16 + row];
-                xr[t] = sg * x.x;
-                xi[t] = sg * x.y;
-            }
+            for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                if (!tv[m]) continue;
-                const double2 v = vc[m];
+                for (int jb = 0; jb < 4; ++jb) {
+                    if (16 * t + 4 * jb >= n) continue;   // uniform: column group past the RHS
+                    const double2 x = xrow[16 * t + 4 * jb];
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    // Re: vr xr + vi xi ; Im: vr xi - vi xr
-                    cre[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, xr[t], cre[m][t], 0, 0, 0);
-                    cre[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.y, xi[t], cre[m][t], 0, 0, 0);
-                    cim[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, xi[t], cim[m][t], 0, 0, 0);
-                    cim[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-v.y, xr[t], cim[m][t], 0, 0, 0);
+                    for (int m = 0; m < MT; ++m) {
+                        if (!tv[m]) continue;
+                        const double2 v = vc[m];
+                        // Re: vr xr + vi xi ; Im: vr xi - vi xr
+                        are[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.x, x.x, are[m][t][jb], 0, 0, 0);
+                        are[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.y, x.y, are[m][t][jb], 0, 0, 0);
+                        aim[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.x, x.y, aim[m][t][jb], 0, 0, 0);
+                        aim[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(-v.y, x.x, aim[m][t][jb], 0, 0, 0);
+                    }
                 }
-            }
         }
     }
 
     // partial[chunk][j][i]
     double2 *pc = part + (long)blockIdx.y * n * l;
+    const int irow = 4 * ((lane >> 2) & 3) + (lane >> 4);
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = (tile0 + W * m) * 16 + 4 * r + kq;
-                const int j = t * 16 + row;
-                if (i < l && j < n) pc[(long)j * l + i] = make_double2(cre[m][t][r], cim[m][t][r]);
+            for (int jb = 0; jb < 4; ++jb) {
+                const int i = (tile0 + W * m) * 16 + irow;
+                const int j = 16 * t + 4 * jb + jq;
+                if (i < l && j < n) pc[(long)j * l + i] = make_double2(are[m][t][jb], aim[m][t][jb]);
             }
 }
 
@@ -144,36 +151,31 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma(const double2 *__restrict
 // element holds the site's components 2p and 2p+1.  Walking k plane by plane
 // would use half of every X line (the partner plane is reached a plane
 // later, long after the line left L1); here each step covers four sites of
-// both planes of a pair: one 16-byte X load per lane feeds the MFMA steps of
+// both planes of a pair: one 16-byte X element per lane feeds the steps of
 // plane 2p and of plane 2p+1.  K-chunks count pairs of planes (chunk sites of
 // the 6 Vp pair positions).
 template <int MT, int NT>
-__global__ __launch_bounds__(512) void k_proj_dot_mfma_pair(const double2 *__restrict__ V, int l, long vstride,
+__global__ __launch_bounds__(256, 3) void k_proj_dot_mfma_pair(const double2 *__restrict__ V, int l, long vstride,
                                                             const float2 *__restrict__ X, long xstride,
                                                             const int *slots, int n, int Vp, int g5x, long chunk,
                                                             double2 *__restrict__ part)
 {
-    // X is staged through LDS 16 sites at a time (all waves of the workgroup
-    // read the same X; one coalesced load per workgroup instead of a 16-row
-    // gather per wave and step).  chunk and Vp are multiples of 16, so a
-    // 16-site slice never crosses a pair-plane.
-    constexpr int XS = 16, XJ = 16 * NT, XP = XJ + 1;
+    constexpr int XS = 32, XJ = 16 * NT, XP = XJ + 4;
     __shared__ float4 xs[XS * XP];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int W = blockDim.x >> 6;
-    const int row = lane & 15, kq = lane >> 4;
+    const int row = lane & 15, kq = lane >> 4, jq = lane & 3;
     const long K2 = 6L * Vp;
     const long k0 = (long)blockIdx.y * chunk;
     const long k1 = (k0 + chunk < K2) ? k0 + chunk : K2;
 
-    v4d cre[MT][NT], cim[MT][NT];
+    double are[MT][NT][4], aim[MT][NT][4];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            cre[m][t] = (v4d){0, 0, 0, 0};
-            cim[m][t] = (v4d){0, 0, 0, 0};
-        }
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) are[m][t][jb] = aim[m][t][jb] = 0.0;
     const double2 *vp[MT];
     bool vok[MT], tv[MT];
     const int tile0 = blockIdx.x * W * MT + wave;
@@ -202,18 +204,16 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma_pair(const double2 *__res
             ++pp;
         }
     };
-    auto mfma_plane = [&](const double2 (&vc)[MT], const cx<double> (&xc)[NT]) {
+    // conj(V) X on one plane of the pair: Re vr xr + vi xi, Im vr xi - vi xr
+    auto mfma_plane = [&](int t, int jb, const double2 (&vc)[MT], double xr, double xi) {
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             if (!tv[m]) continue;
             const double2 v = vc[m];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                cre[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, xc[t].x, cre[m][t], 0, 0, 0);
-                cre[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.y, xc[t].y, cre[m][t], 0, 0, 0);
-                cim[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, xc[t].y, cim[m][t], 0, 0, 0);
-                cim[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-v.y, xc[t].x, cim[m][t], 0, 0, 0);
-            }
+            are[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.x, xr, are[m][t][jb], 0, 0, 0);
+            are[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.y, xi, are[m][t][jb], 0, 0, 0);
+            aim[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.x, xi, aim[m][t][jb], 0, 0, 0);
+            aim[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(-v.y, xr, aim[m][t][jb], 0, 0, 0);
         }
     };
     if (k0 < k1) load_v(k0);
@@ -221,6 +221,7 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma_pair(const double2 *__res
         __syncthreads();   // the previous slice has been consumed
         {
             const long spp = s0 / Vp, sst = s0 - spp * Vp;
+            const float sg = (g5x && s0 >= 3L * Vp) ? -1.f : 1.f;
             for (int e = (int)threadIdx.x; e < XS * XJ; e += (int)blockDim.x) {
                 const int j = e / XS, ii = e - j * XS;   // sites fastest: contiguous reads of one RHS
                 float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -228,11 +229,10 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma_pair(const double2 *__res
                     const int sj = slots ? slots[j] : j;
                     v = *(const float4 *)(X + (long)sj * xstride + 2 * (spp * (long)Vp + sst + ii));
                 }
-                xs[ii * XP + j] = v;
+                xs[ii * XP + j] = make_float4(sg * v.x, sg * v.y, sg * v.z, sg * v.w);
             }
         }
         __syncthreads();
-        const double sg = (g5x && s0 >= 3L * Vp) ? -1.0 : 1.0;
         const long send = (s0 + XS < k1) ? s0 + XS : k1;
         for (long kb = s0; kb < send; kb += 4) {
             double2 v0[MT], v1[MT];
@@ -242,27 +242,29 @@ __global__ __launch_bounds__(512) void k_proj_dot_mfma_pair(const double2 *__res
                 v1[m] = vn1[m];
             }
             if (kb + 4 < k1) load_v(kb + 4);
-            cx<double> x0[NT], x1[NT];
+            const float4 *xrow = xs + (int)(kb - s0 + kq) * XP + jq;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const float4 v = xs[(int)(kb - s0 + kq) * XP + t * 16 + row];
-                x0[t] = {sg * (double)v.x, sg * (double)v.y};
-                x1[t] = {sg * (double)v.z, sg * (double)v.w};
-            }
-            mfma_plane(v0, x0);
-            mfma_plane(v1, x1);
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) {
+                    if (16 * t + 4 * jb >= n) continue;   // uniform: column group past the RHS
+                    const float4 x = xrow[16 * t + 4 * jb];
+                    mfma_plane(t, jb, v0, (double)x.x, (double)x.y);
+                    mfma_plane(t, jb, v1, (double)x.z, (double)x.w);
+                }
         }
     }
     double2 *pc = part + (long)blockIdx.y * n * l;
+    const int irow = 4 * ((lane >> 2) & 3) + (lane >> 4);
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = (tile0 + W * m) * 16 + 4 * r + kq;
-                const int j = t * 16 + row;
-                if (i < l && j < n) pc[(long)j * l + i] = make_double2(cre[m][t][r], cim[m][t][r]);
+            for (int jb = 0; jb < 4; ++jb) {
+                const int i = (tile0 + W * m) * 16 + irow;
+                const int j = 16 * t + 4 * jb + jq;
+                if (i < l && j < n) pc[(long)j * l + i] = make_double2(are[m][t][jb], aim[m][t][jb]);
             }
 }
 
@@ -281,24 +283,26 @@ __global__ void k_proj_reduce(const double2 *__restrict__ part, int nchunk, int 
 }
 
 // --------------------------------------------------------------- X + V E (MFMA)
-// Y = alpha X + beta (V E).  Output tile D[j][k] (16 RHS x 16 consecutive k) += A[j][i] B[i][k] with
-// A = E (transposed coefficients) and B = V; lane q holds A[j = q%16][i = q/16]
-// and B[i = q/16][k = q%16]; the result row j = 4r + q/16, column k = q%16,
-// so a store instruction writes four runs of 16 consecutive k.
-// Each wave owns 16 consecutive k (one column block) and NT RHS tiles.
-// The coefficients E are staged through LDS 16 vector indices at a time:
-// the four waves of a workgroup share each slice (one coalesced load per
-// workgroup instead of a 16-row gather per wave and step).
+// Y = alpha X + beta (V E).  Output D[j][k] (RHS j, position k) += A[j][i] B[i][k] with A = E
+// (transposed coefficients) and B = V, on v_mfma_f64_4x4x4f64 with its four blocks taken as the
+// four column groups of 16 consecutive k: lane q holds B = V[i = q/16][k = q%16], A = E[j = 4jb +
+// q%4][i = q/16] (the same value in all four blocks) and receives D[j = 4jb + q/16][k = q%16], so a
+// store instruction writes four runs of 16 consecutive k.  Each wave owns 16 consecutive k (one
+// column block) and up to 4 NT RHS in groups of 4 (groups past n are skipped).  The coefficients E
+// are staged through LDS 16 vector indices at a time: the four waves of a workgroup share each
+// slice (one coalesced load per workgroup instead of a 16-row gather per wave and step).
 template <class SX, class SY, int NT>
 __global__ __launch_bounds__(256) void k_proj_expand_mfma(const double2 *__restrict__ V, int l, long vstride,
                                                           const SX *X, long xstride, double alpha,
                                                           SY *Y, long ystride, const int *slots, int n,
                                                           int Vp, const double2 *__restrict__ E, double beta)
 {
-    constexpr int EI = 16, EJ = 16 * NT, EP = EJ + 1;   // slice of E: EI vector indices x EJ RHS (row padded)
+    // slice of E: EI vector indices x EJ RHS (rows padded so the four rows a lane group reads sit at
+    // different bank offsets)
+    constexpr int EI = 16, EJ = 16 * NT, EP = EJ + 4;
     __shared__ double2 es[EI * EP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int col = lane & 15, iq = lane >> 4;
+    const int col = lane & 15, iq = lane >> 4, jq = lane & 3;
     const long K = 12L * Vp;
     const long kbase = ((long)blockIdx.x * 4 + wave) * 16;
     const long kk = kbase + col;          // B column handled by this lane
@@ -307,12 +311,11 @@ __global__ __launch_bounds__(256) void k_proj_expand_mfma(const double2 *__restr
     const long pl = kk / Vp, st = kk - pl * Vp;
     const long xk = cpos<SX>((int)pl, st, Vp), yk = cpos<SY>((int)pl, st, Vp);
 
-    v4d dre[NT], dim[NT];
+    double dre[NT][4], dim[NT][4];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        dre[t] = (v4d){0, 0, 0, 0};
-        dim[t] = (v4d){0, 0, 0, 0};
-    }
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) dre[t][jb] = dim[t][jb] = 0.0;
     // V of step ib + 4 is requested before the matrix-core work of step ib
     double2 vn = (iq < l && kok) ? V[(long)iq * vstride + kk] : make_double2(0.0, 0.0);
     for (int i0 = 0; i0 < l; i0 += EI) {
@@ -330,26 +333,30 @@ __global__ __launch_bounds__(256) void k_proj_expand_mfma(const double2 *__restr
                 const int i2 = i + 4;
                 vn = (i2 < l && kok) ? V[(long)i2 * vstride + kk] : make_double2(0.0, 0.0);
             }
+            const double2 *erow = es + (ib - i0 + iq) * EP + jq;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                // A row held by this lane: j = q%16, i = q/16 (zero beyond l and n: the slice is padded)
-                const double2 e = es[(ib - i0 + iq) * EP + t * 16 + col];
-                // (e * v): Re = er vr - ei vi ; Im = er vi + ei vr
-                dre[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.x, v.x, dre[t], 0, 0, 0);
-                dre[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-e.y, v.y, dre[t], 0, 0, 0);
-                dim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.x, v.y, dim[t], 0, 0, 0);
-                dim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(e.y, v.x, dim[t], 0, 0, 0);
-            }
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) {
+                    if (16 * t + 4 * jb >= n) continue;   // uniform: RHS group past n
+                    // A element of this lane: j = 4jb + q%4, i = q/16 (zero beyond l and n: the slice is padded)
+                    const double2 e = erow[16 * t + 4 * jb];
+                    // (e * v): Re = er vr - ei vi ; Im = er vi + ei vr
+                    dre[t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(e.x, v.x, dre[t][jb], 0, 0, 0);
+                    dre[t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(-e.y, v.y, dre[t][jb], 0, 0, 0);
+                    dim[t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(e.x, v.y, dim[t][jb], 0, 0, 0);
+                    dim[t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(e.y, v.x, dim[t][jb], 0, 0, 0);
+                }
         }
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int j = t * 16 + 4 * r + iq;
+        for (int jb = 0; jb < 4; ++jb) {
+            const int j = t * 16 + 4 * jb + iq;
             if (j < n && kok) {
                 const int s = slots ? slots[j] : j;
-                cx<double> y = {beta * dre[t][r], beta * dim[t][r]};
+                cx<double> y = {beta * dre[t][jb], beta * dim[t][jb]};
                 if (X) {
                     cx<double> x = ldc<double>(X + (long)s * xstride, xk);
                     y.x = fma(alpha, x.x, y.x);
@@ -382,10 +389,10 @@ __global__ void k_mul_coef(const double2 *C, const double *w, int l, int n, doub
 // ------------------------------------------------------------------ launchers
 long proj_dot_chunk(long K)
 {
-    // split K into about 1024 chunks (each a multiple of 16); with the tile split
+    // split K into about 1024 chunks (each a multiple of 64); with the tile split
     // along y that is 2048 workgroups for l = 200
     long c = (K + 1023) / 1024;
-    c = (c + 15) & ~15L;   // a multiple of 16: the kernels stage X 16 positions at a time
+    c = (c + 63) & ~63L;   // a multiple of 64: the kernels stage X 32 positions at a time
     if (c < 64) c = 64;
     return c;
 }
@@ -423,8 +430,8 @@ hipError_t launch_proj_dot(const double2 *V, int l, long vstride, const S *X, lo
     int nchunk = (int)((K + chunk - 1) / chunk);
     if constexpr (Pair<S>::E == 2) {
         // chunks of pair positions: half as many positions per chunk (rounded up
-        // to a multiple of 16), so at most as many chunks as the partial buffer holds
-        chunk = ((chunk / 2) + 15) & ~15L;
+        // to a multiple of 32), so at most as many chunks as the partial buffer holds
+        chunk = ((chunk / 2) + 31) & ~31L;
         nchunk = (int)((6L * Vp + chunk - 1) / chunk);
     }
     // two vector tiles per wave, up to four waves per workgroup, the
