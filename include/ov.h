@@ -240,7 +240,8 @@ typedef struct {
     double tol;        /* stop when ||D^dag b - A x|| / ||D^dag b|| <= tol (FP64 true residual) */
     int maxiter;       /* cap on inner iterations summed over restarts                         */
     int inner_prec;    /* OV_FP64, OV_FP32 or OV_BF16 arithmetic of the inner CG               */
-    double inner_tol;  /* relative residual reduction per inner solve (e.g. 1e-5 for FP32)     */
+    double inner_tol;  /* relative residual reduction per inner solve (e.g. 1e-5 for FP32); an  */
+                       /* inner solve also stops once its residual is below 0.1 tol ||D^dag b|| */
     int max_restarts;  /* cap on FP64 defect-correction restarts                               */
     int use_deflation; /* apply the uploaded deflation basis at each restart                   */
 } ov_cg_opts;

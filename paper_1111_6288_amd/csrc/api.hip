@@ -1631,12 +1631,14 @@ int norms2(ov_ctx *c, const Batch &b, const double2 *X, CgScalars &s, int nstore
 }
 
 // Inner CG on A e = r0 (r0 given in R64, FP64), e returned in E (precision S),
-// for the RHS of batch bo.  Iteration counts per storage index added to iters.
+// for the RHS of batch bo.  RHS j stops when |r|^2 falls below
+// max(inner_tol^2 |r0|^2, floor2[j]).  Iteration counts per storage index
+// added to iters.
 template <class S>
 int inner_cg(ov_ctx *c, const Batch &bo, const std::vector<int> &grp, const int *fg, const double2 *ca,
              const double2 *cb, const double *mass, const double2 *R64, S *E, S *r, S *p, S *Ap, S *Dp,
-             DovBufs<S> &w, CgScalars &s, int nstore, double inner_tol, int budget, bool use_defl,
-             std::vector<int> &iters, int &total)
+             DovBufs<S> &w, CgScalars &s, int nstore, double inner_tol, const std::vector<double> &floor2,
+             int budget, bool use_defl, std::vector<int> &iters, int &total)
 {
     const long fe = (long)field_elems(c);
     // r = R ; e = 0 (or the deflation guess)
@@ -1691,11 +1693,11 @@ int inner_cg(ov_ctx *c, const Batch &bo, const std::vector<int> &grp, const int 
         HIPCHK(hipStreamSynchronize(c->stream));
         for (int j : bo.slots_h) {
             rr0[j] = h[j];
-            stop[j] = inner_tol * inner_tol * h[j];
+            stop[j] = std::max(inner_tol * inner_tol * h[j], floor2[j]);
         }
     }
     std::vector<int> act(nstore, 0);
-    for (int j : bo.slots_h) act[j] = rr0[j] > 0 ? 1 : 0;
+    for (int j : bo.slots_h) act[j] = rr0[j] > stop[j] ? 1 : 0;
     HIPCHK(h2d(c, s.stop, stop.data(), 8ul * nstore));
     HIPCHK(h2d(c, s.active, act.data(), 4ul * nstore));
 
@@ -1826,8 +1828,12 @@ int api_cg(ov_ctx *c, int nrhs, const std::vector<int> &grp, const double *mass,
         if (todo.empty() || rounds >= o.max_restarts || total >= o.maxiter) break;
         Batch bo;
         CHK(make_batch(c, todo, grp, bo));
-        CHK(inner_cg<S>(c, bo, grp, fg, ca, cb, mass, R64, E, r, p, Ap, Dp, wS, s, n, o.inner_tol, o.maxiter,
-                        o.use_deflation != 0, iters, total));
+        // No inner solve goes below a tenth of the outer target: the last
+        // defect-correction pass only needs the digits still missing.
+        std::vector<double> floor2(n, 0.0);
+        for (int j : todo) floor2[j] = 0.01 * o.tol * o.tol * rhs2[j];
+        CHK(inner_cg<S>(c, bo, grp, fg, ca, cb, mass, R64, E, r, p, Ap, Dp, wS, s, n, o.inner_tol, floor2,
+                        o.maxiter, o.use_deflation != 0, iters, total));
         // X += e (through R64 as an FP64 staging buffer), then the new true residual
         CHK((copy_fields<S, double2>(c, bo, E, R64)));
         {
