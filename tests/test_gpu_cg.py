@@ -81,3 +81,21 @@ def test_cg_resume_from_saved_iterate():
         Ax = api.dov(lat, sp, api.dov(lat, sp, x_end[j], mass[j]), mass[j], dagger=True)
         assert np.linalg.norm(rhs - Ax) / np.linalg.norm(rhs) <= 3e-10
     ctx.close()
+
+
+def test_inner_solve_stops_at_a_tenth_of_the_target():
+    """An inner solve ends once its residual is below 0.1 tol ||D^dag b||, even when
+    inner_tol asks for more: with FP64 inner arithmetic and inner_tol = 1e-14 the one pass
+    stops near 0.1 tol, and the FP64 true residual is within tol."""
+    L, bc = (4, 4, 6, 8), (2, 0, 0, 2)
+    ctx, U, Vs, lam = _setup(L, bc, 81, 40, 0.02, 4)
+    b = _t(synth.gaussian_spinors(L, 3, 82))
+    tol = 1e-8
+    kw = dict(fields=[0, 1, 0], mass=[0.05, 0.1, 0.2], tol=tol, inner_prec="fp64", inner_tol=1e-14)
+    _, rep = ctx.deflated_cg(b, **kw)
+    _, rep_tight = ctx.deflated_cg(b, **dict(kw, tol=1e-11))
+    for r, rt in zip(rep, rep_tight):
+        assert r["status"] == 0 and r["restarts"] == 1, r
+        assert 1e-11 < r["relres"] <= tol, r
+        assert r["iters"] < rt["iters"], (r, rt)
+    ctx.close()
