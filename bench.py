@@ -397,14 +397,21 @@ for n, l in runs:
     t0 = time.perf_counter()
     api.dov(lat, sp, x, M)
     out.append(time.perf_counter() - t0)
-print(json.dumps(out))
+api.dslash(lat, x, 1)
+td = []
+for _ in range(3):
+    t0 = time.perf_counter()
+    api.dslash(lat, x, 1)
+    td.append(time.perf_counter() - t0)
+print(json.dumps({"runs": out, "hw": min(td)}))
 """
 
 
 def _oracle_dov_seconds(runs, threads):
     """Wall times of FP64 oracle D(m) applications (order n, l small-space vectors, for each
-    (n, l) in runs) on one point source at 24^3 x 48, in a child process with `threads` OpenMP
-    threads (the oracle's thread count is fixed when it loads)."""
+    (n, l) in runs) on one point source at 24^3 x 48, and the best of three H_w applications on
+    it, in a child process with `threads` OpenMP threads (the oracle's thread count is fixed when
+    it loads)."""
     import subprocess
 
     env = dict(os.environ, OMP_NUM_THREADS=str(threads))
@@ -413,7 +420,8 @@ def _oracle_dov_seconds(runs, threads):
                        capture_output=True, text=True, timeout=900)
     if r.returncode != 0:
         raise RuntimeError(f"oracle sample failed: {r.stderr[-2000:]}")
-    return json.loads(r.stdout.strip().splitlines()[-1])
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    return res["runs"], res["hw"]
 
 
 def cpu_baseline():
@@ -425,10 +433,10 @@ def cpu_baseline():
     cost, linear in l).  A 1-thread run of the n = 1, l = 0 sample gives the speed of one core.
     """
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    t300, t1_0, t1_8 = _oracle_dov_seconds([[NPOLY, 8], [1, 0], [1, 8]], threads)
+    (t300, t1_0, t1_8), t_hw = _oracle_dov_seconds([[NPOLY, 8], [1, 0], [1, 8]], threads)
     per_vec = max(t1_8 - t1_0, 0.0) / 8.0
     t_apply = t300 + (LSMALL - 8) * per_vec
-    (one,) = _oracle_dov_seconds([[1, 0]], 1)
+    (one,), t_hw1 = _oracle_dov_seconds([[1, 0]], 1)
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -446,6 +454,8 @@ def cpu_baseline():
         "one_thread": {"n1_l0_seconds": round(one, 3), "n1_l0_seconds_all_threads": round(t1_0, 3),
                        "parallel_speedup": round(one / max(t1_0, 1e-9), 2),
                        "est_seconds_per_apply": round(t_apply * one / max(t1_0, 1e-9), 1)},
+        "hw_dslash_seconds": {"all_threads": round(t_hw, 4), "one_thread": round(t_hw1, 4)},
+        "seconds_per_apply": round(t_apply, 2),
     }
 
 
@@ -545,6 +555,8 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle on host cores)", file=sys.stderr, flush=True)
         cpu = cpu_baseline()
+        # host cores one GPU stands for: CPU seconds x cores per GPU second, per apply
+        cpu["equivalent_cores"] = round(cpu["seconds_per_apply"] * cpu["cores"] * value)
 
     line = {
         "metric": "D_ov applies/s at 24^3x48 (dslash HBM GB/s), mixed+multiRHS vs FP64 at 1e-10",
