@@ -36,24 +36,36 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 //
 // Workgroup (y, c) = W waves (W = blockDim / 64) owns K-chunk c and the
 // vector tiles y W MT + w + W m (m < MT) of its waves w, with all RHS (up to
-// 16 NT).  The launcher takes W = 4 and MT = 2: three waves fit per SIMD, so
+// 4 NJ).  The launcher takes W = 4 and MT = 2: three waves fit per SIMD, so
 // three such workgroups share a CU, where one workgroup holding all 13 tiles
 // of l = 200 (7 waves) would leave it at 7 waves.  X is staged through LDS
-// 32 positions at a time, with the g5 sign applied there: all waves of the
-// workgroup read the same X, so one coalesced load per workgroup replaces a
-// 16-row gather per wave and step.  chunk and Vp are multiples of 32, so a
-// slice lies in one plane (one pair-plane for the paired layout) and on one
-// side of the g5 sign change.
+// 64 positions at a time (53 KB; three workgroups fill the CU's LDS), with the
+// g5 sign applied there: all waves of the workgroup read the same X, so one
+// coalesced load per workgroup replaces a 16-row gather per wave and step.
+// chunk and Vp are multiples of 64, so a slice lies in one plane (one
+// pair-plane for the paired layout) and on one side of the g5 sign change.
 //
-// Row padding of the staged X: rows of XJ + 4 elements put the four k rows a
-// lane group reads at different bank offsets.
-template <class S, int MT, int NT>
+// NJ is the number of 4-column RHS groups (n <= 4 NJ), a template argument so
+// that the matrix-core steps of a wave form one block without branches (a
+// uniform branch per group split it into short dependent chains).  Tiles past
+// l are computed on zeros rather than branched around: the matrix cores are
+// not what bounds these kernels.
+//
+// Row padding of the staged X: rows of XP elements put the four k rows a lane
+// group reads at different bank offsets (XP x 16 bytes = 64 x odd mod 256).
+template <int NJ>
+__host__ __device__ constexpr int xpad()
+{
+    return 4 * NJ + ((NJ % 2 == 0) ? 4 : 8);
+}
+
+template <class S, int MT, int NJ>
 __global__ __launch_bounds__(256, 3) void k_proj_dot_mfma(const double2 *__restrict__ V, int l, long vstride,
                                                        const S *__restrict__ X, long xstride,
                                                        const int *slots, int n, int Vp, int g5x, long chunk,
                                                        double2 *__restrict__ part)
 {
-    constexpr int XS = 32, XJ = 16 * NT, XP = XJ + 4;
+    constexpr int XS = 64, XJ = 4 * NJ, XP = xpad<NJ>();
     __shared__ double2 xs[XS * XP];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int W = blockDim.x >> 6;
@@ -62,21 +74,18 @@ __global__ __launch_bounds__(256, 3) void k_proj_dot_mfma(const double2 *__restr
     const long k0 = (long)blockIdx.y * chunk;
     const long k1 = (k0 + chunk < K) ? k0 + chunk : K;
 
-    double are[MT][NT][4], aim[MT][NT][4];
+    double are[MT][NJ], aim[MT][NJ];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int jb = 0; jb < 4; ++jb) are[m][t][jb] = aim[m][t][jb] = 0.0;
+        for (int g = 0; g < NJ; ++g) are[m][g] = aim[m][g] = 0.0;
 
     const double2 *vp[MT];
-    bool vok[MT], tv[MT];
+    bool vok[MT];
     const int tile0 = blockIdx.x * W * MT + wave;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         const int i = (tile0 + W * m) * 16 + row;
-        tv[m] = (tile0 + W * m) * 16 < l;   // wave-uniform: tiles past l skip their matrix-core work
         vok[m] = i < l;
         vp[m] = V + (long)(vok[m] ? i : 0) * vstride;
     }
@@ -87,6 +96,21 @@ __global__ __launch_bounds__(256, 3) void k_proj_dot_mfma(const double2 *__restr
         const bool kin = k < k1;
 #pragma unroll
         for (int m = 0; m < MT; ++m) vn[m] = (kin && vok[m]) ? vp[m][k] : make_double2(0.0, 0.0);
+    };
+    // conj(V) X: Re vr xr + vi xi, Im vr xi - vi xr
+    auto step = [&](const double2 (&vc)[MT], const double2 *xrow) {
+#pragma unroll
+        for (int g = 0; g < NJ; ++g) {
+            const double2 x = xrow[4 * g];
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const double2 v = vc[m];
+                are[m][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.x, x.x, are[m][g], 0, 0, 0);
+                aim[m][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.x, x.y, aim[m][g], 0, 0, 0);
+                are[m][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.y, x.y, are[m][g], 0, 0, 0);
+                aim[m][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(-v.y, x.x, aim[m][g], 0, 0, 0);
+            }
+        }
     };
     if (k0 < k1) load_v(k0);
     for (long s0 = k0; s0 < k1; s0 += XS) {
@@ -112,23 +136,7 @@ __global__ __launch_bounds__(256, 3) void k_proj_dot_mfma(const double2 *__restr
             for (int m = 0; m < MT; ++m) vc[m] = vn[m];
             if (kb + 4 < k1) load_v(kb + 4);
             const double2 *xrow = xs + (int)(kb - s0 + kq) * XP + jq;
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int jb = 0; jb < 4; ++jb) {
-                    if (16 * t + 4 * jb >= n) continue;   // uniform: column group past the RHS
-                    const double2 x = xrow[16 * t + 4 * jb];
-#pragma unroll
-                    for (int m = 0; m < MT; ++m) {
-                        if (!tv[m]) continue;
-                        const double2 v = vc[m];
-                        // Re: vr xr + vi xi ; Im: vr xi - vi xr
-                        are[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.x, x.x, are[m][t][jb], 0, 0, 0);
-                        are[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.y, x.y, are[m][t][jb], 0, 0, 0);
-                        aim[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.x, x.y, aim[m][t][jb], 0, 0, 0);
-                        aim[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(-v.y, x.x, aim[m][t][jb], 0, 0, 0);
-                    }
-                }
+            step(vc, xrow);
         }
     }
 
@@ -138,13 +146,11 @@ __global__ __launch_bounds__(256, 3) void k_proj_dot_mfma(const double2 *__restr
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int jb = 0; jb < 4; ++jb) {
-                const int i = (tile0 + W * m) * 16 + irow;
-                const int j = 16 * t + 4 * jb + jq;
-                if (i < l && j < n) pc[(long)j * l + i] = make_double2(are[m][t][jb], aim[m][t][jb]);
-            }
+        for (int g = 0; g < NJ; ++g) {
+            const int i = (tile0 + W * m) * 16 + irow;
+            const int j = 4 * g + jq;
+            if (i < l && j < n) pc[(long)j * l + i] = make_double2(are[m][g], aim[m][g]);
+        }
 }
 
 // The same contraction for X in the paired FP32 layout, where one 16-byte
@@ -154,13 +160,13 @@ __global__ __launch_bounds__(256, 3) void k_proj_dot_mfma(const double2 *__restr
 // both planes of a pair: one 16-byte X element per lane feeds the steps of
 // plane 2p and of plane 2p+1.  K-chunks count pairs of planes (chunk sites of
 // the 6 Vp pair positions).
-template <int MT, int NT>
+template <int MT, int NJ>
 __global__ __launch_bounds__(256, 3) void k_proj_dot_mfma_pair(const double2 *__restrict__ V, int l, long vstride,
                                                             const float2 *__restrict__ X, long xstride,
                                                             const int *slots, int n, int Vp, int g5x, long chunk,
                                                             double2 *__restrict__ part)
 {
-    constexpr int XS = 32, XJ = 16 * NT, XP = XJ + 4;
+    constexpr int XS = 64, XJ = 4 * NJ, XP = xpad<NJ>();
     __shared__ float4 xs[XS * XP];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int W = blockDim.x >> 6;
@@ -169,20 +175,17 @@ __global__ __launch_bounds__(256, 3) void k_proj_dot_mfma_pair(const double2 *__
     const long k0 = (long)blockIdx.y * chunk;
     const long k1 = (k0 + chunk < K2) ? k0 + chunk : K2;
 
-    double are[MT][NT][4], aim[MT][NT][4];
+    double are[MT][NJ], aim[MT][NJ];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int jb = 0; jb < 4; ++jb) are[m][t][jb] = aim[m][t][jb] = 0.0;
+        for (int g = 0; g < NJ; ++g) are[m][g] = aim[m][g] = 0.0;
     const double2 *vp[MT];
-    bool vok[MT], tv[MT];
+    bool vok[MT];
     const int tile0 = blockIdx.x * W * MT + wave;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
         const int i = (tile0 + W * m) * 16 + row;
-        tv[m] = (tile0 + W * m) * 16 < l;   // wave-uniform: tiles past l skip their matrix-core work
         vok[m] = i < l;
         vp[m] = V + (long)(vok[m] ? i : 0) * vstride;
     }
@@ -204,16 +207,24 @@ __global__ __launch_bounds__(256, 3) void k_proj_dot_mfma_pair(const double2 *__
             ++pp;
         }
     };
-    // conj(V) X on one plane of the pair: Re vr xr + vi xi, Im vr xi - vi xr
-    auto mfma_plane = [&](int t, int jb, const double2 (&vc)[MT], double xr, double xi) {
+    // conj(V) X on both planes of the pair: Re vr xr + vi xi, Im vr xi - vi xr
+    auto step = [&](const double2 (&v0)[MT], const double2 (&v1)[MT], const float4 *xrow) {
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            if (!tv[m]) continue;
-            const double2 v = vc[m];
-            are[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.x, xr, are[m][t][jb], 0, 0, 0);
-            are[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.y, xi, are[m][t][jb], 0, 0, 0);
-            aim[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(v.x, xi, aim[m][t][jb], 0, 0, 0);
-            aim[m][t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(-v.y, xr, aim[m][t][jb], 0, 0, 0);
+        for (int g = 0; g < NJ; ++g) {
+            const float4 x = xrow[4 * g];
+            const double x0r = x.x, x0i = x.y, x1r = x.z, x1i = x.w;
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const double2 a = v0[m], b = v1[m];
+                are[m][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(a.x, x0r, are[m][g], 0, 0, 0);
+                aim[m][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(a.x, x0i, aim[m][g], 0, 0, 0);
+                are[m][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(a.y, x0i, are[m][g], 0, 0, 0);
+                aim[m][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(-a.y, x0r, aim[m][g], 0, 0, 0);
+                are[m][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(b.x, x1r, are[m][g], 0, 0, 0);
+                aim[m][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(b.x, x1i, aim[m][g], 0, 0, 0);
+                are[m][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(b.y, x1i, are[m][g], 0, 0, 0);
+                aim[m][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(-b.y, x1r, aim[m][g], 0, 0, 0);
+            }
         }
     };
     if (k0 < k1) load_v(k0);
@@ -243,15 +254,7 @@ __global__ __launch_bounds__(256, 3) void k_proj_dot_mfma_pair(const double2 *__
             }
             if (kb + 4 < k1) load_v(kb + 4);
             const float4 *xrow = xs + (int)(kb - s0 + kq) * XP + jq;
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int jb = 0; jb < 4; ++jb) {
-                    if (16 * t + 4 * jb >= n) continue;   // uniform: column group past the RHS
-                    const float4 x = xrow[16 * t + 4 * jb];
-                    mfma_plane(t, jb, v0, (double)x.x, (double)x.y);
-                    mfma_plane(t, jb, v1, (double)x.z, (double)x.w);
-                }
+            step(v0, v1, xrow);
         }
     }
     double2 *pc = part + (long)blockIdx.y * n * l;
@@ -259,13 +262,11 @@ __global__ __launch_bounds__(256, 3) void k_proj_dot_mfma_pair(const double2 *__
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-            for (int jb = 0; jb < 4; ++jb) {
-                const int i = (tile0 + W * m) * 16 + irow;
-                const int j = 16 * t + 4 * jb + jq;
-                if (i < l && j < n) pc[(long)j * l + i] = make_double2(are[m][t][jb], aim[m][t][jb]);
-            }
+        for (int g = 0; g < NJ; ++g) {
+            const int i = (tile0 + W * m) * 16 + irow;
+            const int j = 4 * g + jq;
+            if (i < l && j < n) pc[(long)j * l + i] = make_double2(are[m][g], aim[m][g]);
+        }
 }
 
 // C[j][i] = sum_c part[c][j][i]  (fixed order)
@@ -288,34 +289,34 @@ __global__ void k_proj_reduce(const double2 *__restrict__ part, int nchunk, int 
 // four column groups of 16 consecutive k: lane q holds B = V[i = q/16][k = q%16], A = E[j = 4jb +
 // q%4][i = q/16] (the same value in all four blocks) and receives D[j = 4jb + q/16][k = q%16], so a
 // store instruction writes four runs of 16 consecutive k.  Each wave owns 16 consecutive k (one
-// column block) and up to 4 NT RHS in groups of 4 (groups past n are skipped).  The coefficients E
-// are staged through LDS 16 vector indices at a time: the four waves of a workgroup share each
-// slice (one coalesced load per workgroup instead of a 16-row gather per wave and step).
-template <class SX, class SY, int NT>
-__global__ __launch_bounds__(256) void k_proj_expand_mfma(const double2 *__restrict__ V, int l, long vstride,
+// column block) and up to 4 NJ RHS in NJ groups of 4.  The coefficients E
+// are the same for every position; they are staged through LDS 16 vector indices at a time and
+// the eight waves of a workgroup (128 positions) share each slice.  Every workgroup re-reads all of
+// E from L2, so wider workgroups cut that traffic; 16 waves lost more to the barriers.  At most 80
+// VGPRs (six waves per SIMD) keep enough V loads in flight.
+template <class SX, class SY, int NJ>
+__global__ __launch_bounds__(512, 6) void k_proj_expand_mfma(const double2 *__restrict__ V, int l, long vstride,
                                                           const SX *X, long xstride, double alpha,
                                                           SY *Y, long ystride, const int *slots, int n,
                                                           int Vp, const double2 *__restrict__ E, double beta)
 {
     // slice of E: EI vector indices x EJ RHS (rows padded so the four rows a lane group reads sit at
     // different bank offsets)
-    constexpr int EI = 16, EJ = 16 * NT, EP = EJ + 4;
+    constexpr int EI = 16, EJ = 4 * NJ, EP = xpad<NJ>();
     __shared__ double2 es[EI * EP];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, iq = lane >> 4, jq = lane & 3;
     const long K = 12L * Vp;
-    const long kbase = ((long)blockIdx.x * 4 + wave) * 16;
+    const long kbase = ((long)blockIdx.x * (blockDim.x >> 6) + wave) * 16;
     const long kk = kbase + col;          // B column handled by this lane
     const bool kok = kk < K;              // waves past the end still take part in the barriers
     // the 16 columns of a wave lie in one plane (Vp is a multiple of 16)
     const long pl = kk / Vp, st = kk - pl * Vp;
     const long xk = cpos<SX>((int)pl, st, Vp), yk = cpos<SY>((int)pl, st, Vp);
 
-    double dre[NT][4], dim[NT][4];
+    double dre[NJ], dim[NJ];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int jb = 0; jb < 4; ++jb) dre[t][jb] = dim[t][jb] = 0.0;
+    for (int g = 0; g < NJ; ++g) dre[g] = dim[g] = 0.0;
     // V of step ib + 4 is requested before the matrix-core work of step ib
     double2 vn = (iq < l && kok) ? V[(long)iq * vstride + kk] : make_double2(0.0, 0.0);
     for (int i0 = 0; i0 < l; i0 += EI) {
@@ -335,36 +336,31 @@ __global__ __launch_bounds__(256) void k_proj_expand_mfma(const double2 *__restr
             }
             const double2 *erow = es + (ib - i0 + iq) * EP + jq;
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int jb = 0; jb < 4; ++jb) {
-                    if (16 * t + 4 * jb >= n) continue;   // uniform: RHS group past n
-                    // A element of this lane: j = 4jb + q%4, i = q/16 (zero beyond l and n: the slice is padded)
-                    const double2 e = erow[16 * t + 4 * jb];
-                    // (e * v): Re = er vr - ei vi ; Im = er vi + ei vr
-                    dre[t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(e.x, v.x, dre[t][jb], 0, 0, 0);
-                    dre[t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(-e.y, v.y, dre[t][jb], 0, 0, 0);
-                    dim[t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(e.x, v.y, dim[t][jb], 0, 0, 0);
-                    dim[t][jb] = __builtin_amdgcn_mfma_f64_4x4x4f64(e.y, v.x, dim[t][jb], 0, 0, 0);
-                }
+            for (int g = 0; g < NJ; ++g) {
+                // A element of this lane: j = 4g + q%4, i = q/16 (zero beyond l and n: the slice is padded)
+                const double2 e = erow[4 * g];
+                // (e * v): Re = er vr - ei vi ; Im = er vi + ei vr
+                dre[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(e.x, v.x, dre[g], 0, 0, 0);
+                dim[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(e.x, v.y, dim[g], 0, 0, 0);
+                dre[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(-e.y, v.y, dre[g], 0, 0, 0);
+                dim[g] = __builtin_amdgcn_mfma_f64_4x4x4f64(e.y, v.x, dim[g], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int jb = 0; jb < 4; ++jb) {
-            const int j = t * 16 + 4 * jb + iq;
-            if (j < n && kok) {
-                const int s = slots ? slots[j] : j;
-                cx<double> y = {beta * dre[t][jb], beta * dim[t][jb]};
-                if (X) {
-                    cx<double> x = ldc<double>(X + (long)s * xstride, xk);
-                    y.x = fma(alpha, x.x, y.x);
-                    y.y = fma(alpha, x.y, y.y);
-                }
-                stc<double>(Y + (long)s * ystride, yk, y);
+    for (int g = 0; g < NJ; ++g) {
+        const int j = 4 * g + iq;
+        if (j < n && kok) {
+            const int s = slots ? slots[j] : j;
+            cx<double> y = {beta * dre[g], beta * dim[g]};
+            if (X) {
+                cx<double> x = ldc<double>(X + (long)s * xstride, xk);
+                y.x = fma(alpha, x.x, y.x);
+                y.y = fma(alpha, x.y, y.y);
             }
+            stc<double>(Y + (long)s * ystride, yk, y);
         }
+    }
 }
 
 // E[j][i] = sgn(lambda_i) C[j][i] - D[j][i]
@@ -387,17 +383,28 @@ __global__ void k_mul_coef(const double2 *C, const double *w, int l, int n, doub
 }
 
 // ------------------------------------------------------------------ launchers
+// RHS column groups of 4 the kernels are built for (n <= 48); a batch takes the
+// smallest that holds it.
+#define OV_NJ_LIST(M) \
+    OV_DOT_CASE(M, 1) OV_DOT_CASE(M, 2) OV_DOT_CASE(M, 3) OV_DOT_CASE(M, 4) OV_DOT_CASE(M, 6) OV_DOT_CASE(M, 8) \
+    OV_DOT_CASE(M, 9) OV_DOT_CASE(M, 12)
+static int proj_groups(int n)
+{
+    const int g = (n + 3) / 4;
+    return g <= 4 ? g : g <= 6 ? 6 : g <= 8 ? 8 : g <= 9 ? 9 : 12;
+}
+
 long proj_dot_chunk(long K)
 {
-    // split K into about 1024 chunks (each a multiple of 64); with the tile split
+    // split K into about 1024 chunks (each a multiple of 128); with the tile split
     // along y that is 2048 workgroups for l = 200
     long c = (K + 1023) / 1024;
-    c = (c + 63) & ~63L;   // a multiple of 64: the kernels stage X 32 positions at a time
+    c = (c + 127) & ~127L;   // a multiple of 128: the kernels stage X 64 positions at a time
     if (c < 64) c = 64;
     return c;
 }
 
-template <class S, int MT, int NT>
+template <class S, int MT, int NJ>
 static void launch_dot_mt(const double2 *V, int l, long vstride, const S *X, long xstride, const int *slots,
                           int n, int Vp, int g5x, long chunk, int nchunk, double2 *part, int waves, hipStream_t st)
 {
@@ -405,17 +412,17 @@ static void launch_dot_mt(const double2 *V, int l, long vstride, const S *X, lon
     const int ny = (tiles + waves * MT - 1) / (waves * MT);
     // the ny workgroups of a K-chunk are consecutive in dispatch order, so they
     // run at the same time and the second one reads the chunk of X from L2
-    hipLaunchKernelGGL((k_proj_dot_mfma<S, MT, NT>), dim3(ny, nchunk), dim3(64 * waves), 0, st, V, l, vstride, X,
+    hipLaunchKernelGGL((k_proj_dot_mfma<S, MT, NJ>), dim3(ny, nchunk), dim3(64 * waves), 0, st, V, l, vstride, X,
                        xstride, slots, n, Vp, g5x, chunk, part);
 }
 
-template <int MT, int NT>
+template <int MT, int NJ>
 static void launch_dot_pair(const double2 *V, int l, long vstride, const float2 *X, long xstride, const int *slots,
                             int n, int Vp, int g5x, long chunk, int nchunk, double2 *part, int waves, hipStream_t st)
 {
     const int tiles = (l + 15) / 16;
     const int ny = (tiles + waves * MT - 1) / (waves * MT);
-    hipLaunchKernelGGL((k_proj_dot_mfma_pair<MT, NT>), dim3(ny, nchunk), dim3(64 * waves), 0, st, V, l, vstride, X,
+    hipLaunchKernelGGL((k_proj_dot_mfma_pair<MT, NJ>), dim3(ny, nchunk), dim3(64 * waves), 0, st, V, l, vstride, X,
                        xstride, slots, n, Vp, g5x, chunk, part);
 }
 
@@ -430,8 +437,8 @@ hipError_t launch_proj_dot(const double2 *V, int l, long vstride, const S *X, lo
     int nchunk = (int)((K + chunk - 1) / chunk);
     if constexpr (Pair<S>::E == 2) {
         // chunks of pair positions: half as many positions per chunk (rounded up
-        // to a multiple of 32), so at most as many chunks as the partial buffer holds
-        chunk = ((chunk / 2) + 31) & ~31L;
+        // to a multiple of 64), so at most as many chunks as the partial buffer holds
+        chunk = ((chunk / 2) + 63) & ~63L;
         nchunk = (int)((6L * Vp + chunk - 1) / chunk);
     }
     // two vector tiles per wave, up to four waves per workgroup, the
@@ -439,22 +446,24 @@ hipError_t launch_proj_dot(const double2 *V, int l, long vstride, const S *X, lo
     const int tiles = (l + 15) / 16;
     const int mt = tiles >= 2 ? 2 : 1;
     const int waves = std::min(4, (tiles + mt - 1) / mt);
-    const int nt = (n + 15) / 16;
+    const int nj = proj_groups(n);
     if constexpr (Pair<S>::E == 2) {
 #define OV_DOT_CASE(M, N) \
-    if (mt == M && nt == N) \
-    launch_dot_pair<M, N>(V, l, vstride, X, xstride, slots, n, Vp, g5x, chunk, nchunk, part, waves, st)
-        OV_DOT_CASE(1, 1); else OV_DOT_CASE(1, 2); else OV_DOT_CASE(1, 3);
-        else OV_DOT_CASE(2, 1); else OV_DOT_CASE(2, 2); else OV_DOT_CASE(2, 3);
-        else return hipErrorInvalidValue;
+    case N: launch_dot_pair<M, N>(V, l, vstride, X, xstride, slots, n, Vp, g5x, chunk, nchunk, part, waves, st); break;
+        if (mt == 2) {
+            switch (nj) { OV_NJ_LIST(2) default: return hipErrorInvalidValue; }
+        } else {
+            switch (nj) { OV_NJ_LIST(1) default: return hipErrorInvalidValue; }
+        }
 #undef OV_DOT_CASE
     } else {
 #define OV_DOT_CASE(M, N) \
-    if (mt == M && nt == N) \
-    launch_dot_mt<S, M, N>(V, l, vstride, X, xstride, slots, n, Vp, g5x, chunk, nchunk, part, waves, st)
-        OV_DOT_CASE(1, 1); else OV_DOT_CASE(1, 2); else OV_DOT_CASE(1, 3);
-        else OV_DOT_CASE(2, 1); else OV_DOT_CASE(2, 2); else OV_DOT_CASE(2, 3);
-        else return hipErrorInvalidValue;
+    case N: launch_dot_mt<S, M, N>(V, l, vstride, X, xstride, slots, n, Vp, g5x, chunk, nchunk, part, waves, st); break;
+        if (mt == 2) {
+            switch (nj) { OV_NJ_LIST(2) default: return hipErrorInvalidValue; }
+        } else {
+            switch (nj) { OV_NJ_LIST(1) default: return hipErrorInvalidValue; }
+        }
 #undef OV_DOT_CASE
     }
     const int nl = n * l;
@@ -470,17 +479,15 @@ hipError_t launch_proj_expand(const double2 *V, int l, long vstride, const SX *X
     if (n <= 0) return hipSuccess;
     if (n > 48) return hipErrorInvalidValue;
     const long K = 12L * Vp;
-    const int nblk = (int)((K + 63) / 64);
-    const int nt = (n + 15) / 16;
-    if (nt == 1)
-        hipLaunchKernelGGL((k_proj_expand_mfma<SX, SY, 1>), dim3(nblk), dim3(256), 0, st, V, l, vstride, X, xstride,
-                           alpha, Y, ystride, slots, n, Vp, E, beta);
-    else if (nt == 2)
-        hipLaunchKernelGGL((k_proj_expand_mfma<SX, SY, 2>), dim3(nblk), dim3(256), 0, st, V, l, vstride, X, xstride,
-                           alpha, Y, ystride, slots, n, Vp, E, beta);
-    else
-        hipLaunchKernelGGL((k_proj_expand_mfma<SX, SY, 3>), dim3(nblk), dim3(256), 0, st, V, l, vstride, X, xstride,
-                           alpha, Y, ystride, slots, n, Vp, E, beta);
+    // 8 waves of 16 positions per workgroup: each staged slice of E serves 128 positions
+    const int nblk = (int)((K + 127) / 128);
+#define OV_DOT_CASE(M, N)                                                                                      \
+    case N:                                                                                                    \
+        hipLaunchKernelGGL((k_proj_expand_mfma<SX, SY, N>), dim3(nblk), dim3(512), 0, st, V, l, vstride, X,   \
+                           xstride, alpha, Y, ystride, slots, n, Vp, E, beta);                                 \
+        break;
+    switch (proj_groups(n)) { OV_NJ_LIST(0) default: return hipErrorInvalidValue; }
+#undef OV_DOT_CASE
     return hipGetLastError();
 }
 
