@@ -18,17 +18,15 @@
 
 namespace ov {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-
 // --------------------------------------------------------------- V^dag X (MFMA)
 // The matrix-core instruction is v_mfma_f64_4x4x4f64: four independent
 // 4x4x4 products per wavefront.  Its lane layout, as measured on gfx950:
 // block b = (lane >> 2) & 3; A_b[i][k] comes from lane i + 4b + 16k,
 // B_b[k][j] from lane j + 4b + 16k, and D_b[i][j] lands in lane 16i + 4b + j.
 // The four blocks are taken as the four row groups of one 16-row tile: lane
-// q holds A = V[row q%16][k q/16], B = X[k q/16][column 4jb + q%4] (the same
-// value in all four blocks) and receives C[row 4((q>>2)&3) + q/16][column
-// 4jb + q%4].  Four such instructions do the work of one 16x16x4 step, but on
+// q holds A = V[row q%16][k q/16], B = X[k q/16][column 4g + q%4] for RHS
+// group g (the same value in all four blocks) and receives
+// C[row 4((q>>2)&3) + q/16][column 4g + q%4].  Four such instructions do the work of one 16x16x4 step, but on
 // gfx950 they sustain ~72 TFLOP/s of FP64 against ~47 for v_mfma_f64_16x16x4f64
 // (register-only loops of independent instructions), and RHS columns come in
 // groups of 4, so a batch of 36 RHS wastes nothing where 16-wide tiles pad it
@@ -39,7 +37,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // 4 NJ).  The launcher takes W = 4 and MT = 2: three waves fit per SIMD, so
 // three such workgroups share a CU, where one workgroup holding all 13 tiles
 // of l = 200 (7 waves) would leave it at 7 waves.  X is staged through LDS
-// 64 positions at a time (53 KB; three workgroups fill the CU's LDS), with the
+// 64 positions at a time (at most 53 KB, so three workgroups fit a CU), with the
 // g5 sign applied there: all waves of the workgroup read the same X, so one
 // coalesced load per workgroup replaces a 16-row gather per wave and step.
 // chunk and Vp are multiples of 64, so a slice lies in one plane (one
@@ -48,8 +46,9 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // NJ is the number of 4-column RHS groups (n <= 4 NJ), a template argument so
 // that the matrix-core steps of a wave form one block without branches (a
 // uniform branch per group split it into short dependent chains).  Tiles past
-// l are computed on zeros rather than branched around: the matrix cores are
-// not what bounds these kernels.
+// l are computed on zeros rather than branched around: a copy of the K loop
+// for one tile, taken by the waves whose second tile lies past l, measured no
+// faster.
 //
 // Row padding of the staged X: rows of XP elements put the four k rows a lane
 // group reads at different bank offsets (XP x 16 bytes = 64 x odd mod 256).
