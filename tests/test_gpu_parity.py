@@ -573,10 +573,12 @@ def test_workspace_reuse_across_precisions_keeps_padding_zero():
             assert _rel(y[j], ref[j]) < tol, (prec, j)
 
 
-@pytest.mark.parametrize("l,nrhs", [(129, 37), (200, 17), (256, 48)])
+@pytest.mark.parametrize("l,nrhs", [(129, 37), (200, 17), (256, 48), (200, 29), (64, 14), (33, 3)])
 def test_sign_large_small_space(l, nrhs):
     """Small spaces of more than 8 tiles of 16 vectors (the V^dag X kernel then spreads the
-    tiles over several workgroups per K-chunk), ragged l and RHS counts, against the oracle."""
+    tiles over several workgroups per K-chunk), ragged l and RHS counts, against the oracle.
+    The RHS counts reach every compiled group count of 4 columns (3 -> 1, 14 -> 4, 17 -> 6,
+    29 -> 8, 37 and 48 -> 12; 36 per group is the full-size test's)."""
     L, bc = (4, 4, 4, 6), (2, 0, 0, 2)
     U = synth.su3_links(L, 0.3, 61)
     ctx = make_ctx(L, bc, U, (2 / 3,), (0.2,))
